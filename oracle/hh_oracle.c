@@ -1,0 +1,343 @@
+/*
+ * hh_oracle.c -- plain, slow, scalar CPU oracle for HighwayHash as defined in
+ * "Fast keyed hash/pseudo-random function using SIMD multiply and permute"
+ * (Alakuijala, Cox, Wassenberg; arXiv:1612.06257).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, imports or
+ * calls this file.  Only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header, table or constant with the
+ * HIP implementation; the two are written separately and compared by tests.
+ *
+ * Everything is unsigned 64-bit integer arithmetic ("+" is mod 2^64), written
+ * one lane at a time so that each step can be checked against the paper by eye:
+ *
+ *   state      Sec. 4.2: four vectors v0, v1, mul0, mul1 of four 64-bit lanes
+ *   constants  Sec. 4.4: hexadecimal digits of pi, fourth word rebuilt
+ *   Reset      Sec. 4.4: v0 = key ^ C0, v1 = rot32(key) ^ C1, mul0 = C0, mul1 = C1
+ *   ZipperMerge Sec. 4.1: byte permutation 7 8 6 9 D A 4 B 0 F 1 E 5 2 C 3
+ *   Update     Sec. 4.2: the seven-statement listing, in order
+ *   Remainder  Sec. 4.5: size mod 32 into v0, v1 halves rotated, padded packet
+ *   Permute    Sec. 4.3: 32-bit indices 2 3 0 1 6 7 4 5 of v0
+ *   Finalize   Sec. 4.3: four times Update(Permute(v0)), then v0+v1+mul0+mul1
+ *
+ * Readings taken where the paper is silent (each is tested as noted):
+ *   - packet bytes 8i..8i+7 form lane i, little-endian (x86 loads);
+ *   - key word i is lane i;
+ *   - the permutation lists of Sec. 4.1 and 4.3 are written highest element
+ *     first ("i=15 listed first"); the low-first reading violates the paper's
+ *     own requirement 1 and its "swap halves" description (tests check both);
+ *   - size injection adds r*(2^32+1) with the vector class's 64-bit lane add;
+ *   - each 32-bit half of a v1 lane is rotated LEFT by r;
+ *   - the 0..31 tail bytes: the first q = r - r%4 go to packet bytes 0..q-1,
+ *     the last r%4 go to packet bytes 28, 29, 30 (in order), the rest are 0;
+ *   - injection and rotation happen before the padded packet's Update;
+ *   - no remainder step at all when size mod 32 == 0 (including size 0);
+ *   - 4 finalization rounds for every output width; a 128-bit hash is lanes
+ *     0..1 and a 256-bit hash lanes 0..3 of the final sum.
+ * These readings fix the oracle's outputs; no known-answer vectors for the
+ * original release are available, so interoperability with that release is
+ * parity unpinned (the tests pin each step to what the paper does fix).
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#include <pthread.h>
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 4.2: the 1024-bit state, four vectors of four independent 64-bit lanes */
+typedef struct {
+    uint64_t v0[4];
+    uint64_t v1[4];
+    uint64_t mul0[4];
+    uint64_t mul1[4];
+} hh_ref_state;
+
+/* Sec. 4.4: "nothing up my sleeve" constants from the hexadecimal expansion of
+ * pi.  The fraction's 64-bit words w0.. are 243f6a8885a308d3, 13198a2e03707344,
+ * a4093822299f31d0, 082efa98ec4e6c89, 452821e638d01377, be5466cf34e90c6c,
+ * c0ac29b7c97c50dd, ...  Each constant takes three consecutive words for lanes
+ * 3, 2, 1 and replaces the fourth number (lane 0) by the word whose bit k is
+ * set exactly when zero or one of the other three lanes has bit k set, so that
+ * every bit is set in at least one lane.  C0 uses w0..w2, C1 uses w4..w6
+ * (w3 is the fourth number the rule rewrites for C0; w7 likewise for C1). */
+static const uint64_t HH_REF_C0[4] = {
+    0xdbe6d5d5fe4cce2fULL, 0xa4093822299f31d0ULL,
+    0x13198a2e03707344ULL, 0x243f6a8885a308d3ULL};
+static const uint64_t HH_REF_C1[4] = {
+    0x3bd3de18c707ef82ULL, 0xc0ac29b7c97c50ddULL,
+    0xbe5466cf34e90c6cULL, 0x452821e638d01377ULL};
+
+/* Sec. 4.1: the final zipper permutation as printed, element i=15 first. */
+static const uint8_t HH_REF_ZIPPER_PRINTED[16] = {
+    0x7, 0x8, 0x6, 0x9, 0xD, 0xA, 0x4, 0xB, 0x0, 0xF, 0x1, 0xE, 0x5, 0x2, 0xC, 0x3};
+
+/* Sec. 4.3: indices of 32-bit parts used to permute v0, as printed
+ * (highest 32-bit element first, the same convention as Sec. 4.1). */
+static const uint8_t HH_REF_PERMUTE_PRINTED[8] = {2, 3, 0, 1, 6, 7, 4, 5};
+
+void hh_ref_constants(uint64_t c0[4], uint64_t c1[4]) {
+    for (int i = 0; i < 4; ++i) {
+        c0[i] = HH_REF_C0[i];
+        c1[i] = HH_REF_C1[i];
+    }
+}
+
+static uint64_t lo32(uint64_t x) { return x & 0xffffffffULL; }
+static uint64_t hi32(uint64_t x) { return x >> 32; }
+
+/* swap the two 32-bit halves of a 64-bit lane */
+static uint64_t rot32(uint64_t x) { return (x >> 32) | (x << 32); }
+
+/* little-endian 64-bit word from 8 bytes */
+static uint64_t le64(const uint8_t* b) {
+    uint64_t x = 0;
+    for (int j = 7; j >= 0; --j) x = (x << 8) | b[j];
+    return x;
+}
+
+static void put_le64(uint8_t* b, uint64_t x) {
+    for (int j = 0; j < 8; ++j) b[j] = (uint8_t)(x >> (8 * j));
+}
+
+/* Sec. 4.4: Reset(key). */
+void hh_ref_reset(const uint64_t key[4], hh_ref_state* s) {
+    for (int i = 0; i < 4; ++i) {
+        s->mul0[i] = HH_REF_C0[i];
+        s->mul1[i] = HH_REF_C1[i];
+        s->v0[i] = key[i] ^ HH_REF_C0[i];
+        s->v1[i] = rot32(key[i]) ^ HH_REF_C1[i];
+    }
+}
+
+/* Sec. 4.1: ZipperMerge of one 16-byte lane pair (a = low lane, b = high lane).
+ * S is the pair's bytes (S[0..7] = a little-endian, S[8..15] = b), and result
+ * byte R_i = S[P_i], where P is the printed list read with i=15 first. */
+void hh_ref_zipper_merge(uint64_t a, uint64_t b, uint64_t* ra, uint64_t* rb) {
+    uint8_t S[16], R[16];
+    put_le64(S, a);
+    put_le64(S + 8, b);
+    for (int i = 0; i < 16; ++i) {
+        uint8_t P_i = HH_REF_ZIPPER_PRINTED[15 - i];
+        R[i] = S[P_i];
+    }
+    *ra = le64(R);
+    *rb = le64(R + 8);
+}
+
+/* ZipperMerge of a whole vector: it only combines adjacent lanes (Sec. 4.3),
+ * i.e. lanes (0,1) and (2,3) are zipped independently. */
+static void zipper_merge_vec(const uint64_t v[4], uint64_t out[4]) {
+    hh_ref_zipper_merge(v[0], v[1], &out[0], &out[1]);
+    hh_ref_zipper_merge(v[2], v[3], &out[2], &out[3]);
+}
+
+/* Sec. 4.2: Update(packet), the listing's seven statements in order.
+ * _mm256_mul_epu32(x, y) multiplies the low 32 bits of each lane of x and y
+ * into a 64-bit product; y = v0 >> 32 (resp. v1 >> 32) so the product is
+ * lo32(x) * hi32(v). */
+void hh_ref_update(hh_ref_state* s, const uint64_t packet[4]) {
+    uint64_t zm[4];
+    for (int i = 0; i < 4; ++i) s->v1[i] += packet[i];                   /* v1 += packet */
+    for (int i = 0; i < 4; ++i) s->v1[i] += s->mul0[i];                  /* v1 += mul0 */
+    for (int i = 0; i < 4; ++i)
+        s->mul0[i] ^= lo32(s->v1[i]) * hi32(s->v0[i]);                  /* mul0 ^= mul(v1, v0>>32) */
+    for (int i = 0; i < 4; ++i) s->v0[i] += s->mul1[i];                  /* v0 += mul1 */
+    for (int i = 0; i < 4; ++i)
+        s->mul1[i] ^= lo32(s->v0[i]) * hi32(s->v1[i]);                  /* mul1 ^= mul(v0, v1>>32) */
+    zipper_merge_vec(s->v1, zm);
+    for (int i = 0; i < 4; ++i) s->v0[i] += zm[i];                       /* v0 += ZipperMerge(v1) */
+    zipper_merge_vec(s->v0, zm);
+    for (int i = 0; i < 4; ++i) s->v1[i] += zm[i];                       /* v1 += ZipperMerge(v0) */
+}
+
+/* Sec. 4.3: permute v0 by the printed 32-bit indices.  Element e of a vector
+ * is the 32-bit part e (element 2i = low half of lane i, 2i+1 = high half);
+ * result element e = source element INDEX[7 - e] (highest listed first). */
+void hh_ref_permute(const uint64_t v0[4], uint64_t out[4]) {
+    uint32_t src[8], dst[8];
+    for (int i = 0; i < 4; ++i) {
+        src[2 * i] = (uint32_t)lo32(v0[i]);
+        src[2 * i + 1] = (uint32_t)hi32(v0[i]);
+    }
+    for (int e = 0; e < 8; ++e) dst[e] = src[HH_REF_PERMUTE_PRINTED[7 - e]];
+    for (int i = 0; i < 4; ++i) out[i] = ((uint64_t)dst[2 * i + 1] << 32) | dst[2 * i];
+}
+
+/* rotate a 32-bit value left by r, 1 <= r <= 31 */
+static uint32_t rotl32(uint32_t x, unsigned r) { return (x << r) | (x >> (32 - r)); }
+
+/* Sec. 4.5: the remainder step for the last r = size mod 32 bytes (1..31).
+ * The size mod 32 is broadcast into all eight 32-bit parts and added to v0;
+ * the 32-bit parts of v1 are rotated by the same amount; the tail bytes form
+ * one padded packet (whole 4-byte groups at the start, the last 0..3 bytes in
+ * the packet's most-significant four bytes) which is passed to Update. */
+void hh_ref_remainder(hh_ref_state* s, const uint8_t* tail, size_t r) {
+    uint8_t P[32];
+    uint64_t packet[4];
+    size_t q = r - (r % 4), m = r % 4;
+    uint64_t broadcast = ((uint64_t)r << 32) | (uint64_t)r;
+    for (int i = 0; i < 4; ++i) {
+        s->v0[i] += broadcast;
+        uint32_t lo = rotl32((uint32_t)lo32(s->v1[i]), (unsigned)r);
+        uint32_t hi = rotl32((uint32_t)hi32(s->v1[i]), (unsigned)r);
+        s->v1[i] = ((uint64_t)hi << 32) | lo;
+    }
+    memset(P, 0, sizeof P);
+    for (size_t j = 0; j < q; ++j) P[j] = tail[j];
+    for (size_t j = 0; j < m; ++j) P[28 + j] = tail[q + j];
+    for (int i = 0; i < 4; ++i) packet[i] = le64(P + 8 * i);
+    hh_ref_update(s, packet);
+}
+
+/* Sec. 4.3: `rounds` times Update(Permute(v0)) (4 in the paper), then the sum
+ * of the four state vectors; all four lanes are returned. */
+void hh_ref_finalize(hh_ref_state* s, int rounds, uint64_t sum[4]) {
+    uint64_t q[4];
+    for (int k = 0; k < rounds; ++k) {
+        hh_ref_permute(s->v0, q);
+        hh_ref_update(s, q);
+    }
+    for (int i = 0; i < 4; ++i) sum[i] = s->v0[i] + s->v1[i] + s->mul0[i] + s->mul1[i];
+}
+
+/* Full hash with a chosen number of finalization rounds (the paper uses 4; the
+ * parameter exists for the round-count study of Sec. 4.3). */
+void hh_ref_hash_rounds(const uint64_t key[4], const uint8_t* p, size_t len, int rounds,
+                        uint64_t sum[4]) {
+    hh_ref_state s;
+    uint64_t packet[4];
+    size_t full = len / 32, r = len % 32;
+    hh_ref_reset(key, &s);
+    for (size_t t = 0; t < full; ++t) {
+        for (int i = 0; i < 4; ++i) packet[i] = le64(p + 32 * t + 8 * i);
+        hh_ref_update(&s, packet);
+    }
+    if (r != 0) hh_ref_remainder(&s, p + 32 * full, r);
+    hh_ref_finalize(&s, rounds, sum);
+}
+
+/* 64-bit hash: the lower lane (Sec. 4.3). */
+uint64_t hh_ref_hash64(const uint64_t key[4], const uint8_t* p, size_t len) {
+    uint64_t sum[4];
+    hh_ref_hash_rounds(key, p, len, 4, sum);
+    return sum[0];
+}
+
+void hh_ref_hash128(const uint64_t key[4], const uint8_t* p, size_t len, uint64_t out[2]) {
+    uint64_t sum[4];
+    hh_ref_hash_rounds(key, p, len, 4, sum);
+    out[0] = sum[0];
+    out[1] = sum[1];
+}
+
+void hh_ref_hash256(const uint64_t key[4], const uint8_t* p, size_t len, uint64_t out[4]) {
+    hh_ref_hash_rounds(key, p, len, 4, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 4.5: incremental hashing.  Only size mod 32 enters the hash, so a
+ * stream needs the 1024-bit state plus at most 31 buffered bytes. */
+typedef struct {
+    hh_ref_state s;
+    uint8_t buf[32];
+    uint32_t n; /* buffered bytes, 0..31 */
+} hh_ref_cat;
+
+size_t hh_ref_cat_size(void) { return sizeof(hh_ref_cat); }
+
+void hh_ref_cat_init(hh_ref_cat* c, const uint64_t key[4]) {
+    hh_ref_reset(key, &c->s);
+    c->n = 0;
+}
+
+static void cat_update_packet(hh_ref_cat* c, const uint8_t* bytes32) {
+    uint64_t packet[4];
+    for (int i = 0; i < 4; ++i) packet[i] = le64(bytes32 + 8 * i);
+    hh_ref_update(&c->s, packet);
+}
+
+void hh_ref_cat_append(hh_ref_cat* c, const uint8_t* p, size_t len) {
+    while (len > 0) {
+        c->buf[c->n++] = *p++;
+        --len;
+        if (c->n == 32) {
+            cat_update_packet(c, c->buf);
+            c->n = 0;
+        }
+    }
+}
+
+/* Finish without disturbing the stream: works on a copy of the state.
+ * width_words is 1, 2 or 4 (64, 128 or 256 bits). */
+void hh_ref_cat_finish(const hh_ref_cat* c, int width_words, uint64_t* out) {
+    hh_ref_state s = c->s;
+    uint64_t sum[4];
+    if (c->n != 0) hh_ref_remainder(&s, c->buf, c->n);
+    hh_ref_finalize(&s, 4, sum);
+    for (int i = 0; i < width_words; ++i) out[i] = sum[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batch driver: message j is data[offsets[j] .. offsets[j]+lengths[j]) under
+ * key keys[4*key_idx[j] ..] (key 0 when key_idx is NULL); out holds
+ * width_words words per message, lane 0 first.  Messages are split into
+ * contiguous ranges of roughly equal bytes, one per thread. */
+typedef struct {
+    const uint64_t* keys;
+    const uint32_t* key_idx;
+    const uint8_t* data;
+    const uint64_t* offsets;
+    const uint64_t* lengths;
+    int width_words;
+    uint64_t* out;
+    uint64_t begin, end;
+} batch_job;
+
+static void* batch_worker(void* arg) {
+    batch_job* J = (batch_job*)arg;
+    uint64_t sum[4];
+    for (uint64_t j = J->begin; j < J->end; ++j) {
+        const uint64_t* key = J->keys + 4 * (uint64_t)(J->key_idx ? J->key_idx[j] : 0);
+        hh_ref_hash_rounds(key, J->data + J->offsets[j], (size_t)J->lengths[j], 4, sum);
+        for (int i = 0; i < J->width_words; ++i) J->out[(uint64_t)J->width_words * j + i] = sum[i];
+    }
+    return NULL;
+}
+
+int hh_ref_batch(const uint64_t* keys, const uint32_t* key_idx, const uint8_t* data,
+                 const uint64_t* offsets, const uint64_t* lengths, uint64_t n,
+                 int width_words, uint64_t* out, int n_threads) {
+    enum { MAX_THREADS = 256 };
+    pthread_t tid[MAX_THREADS];
+    batch_job jobs[MAX_THREADS];
+    uint64_t total = 0, acc = 0, j = 0;
+    if (width_words != 1 && width_words != 2 && width_words != 4) return 1;
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > MAX_THREADS) n_threads = MAX_THREADS;
+    for (uint64_t k = 0; k < n; ++k) total += lengths[k] + 64; /* +64: per-message fixed cost */
+    for (int t = 0; t < n_threads; ++t) {
+        uint64_t target = total / (uint64_t)n_threads * (uint64_t)(t + 1);
+        jobs[t].keys = keys;
+        jobs[t].key_idx = key_idx;
+        jobs[t].data = data;
+        jobs[t].offsets = offsets;
+        jobs[t].lengths = lengths;
+        jobs[t].width_words = width_words;
+        jobs[t].out = out;
+        jobs[t].begin = j;
+        while (j < n && (t == n_threads - 1 || acc < target)) {
+            acc += lengths[j] + 64;
+            ++j;
+        }
+        jobs[t].end = j;
+    }
+    int started[MAX_THREADS] = {0};
+    for (int t = 1; t < n_threads; ++t) {
+        started[t] = pthread_create(&tid[t], NULL, batch_worker, &jobs[t]) == 0;
+        if (!started[t]) batch_worker(&jobs[t]); /* no thread: run it here */
+    }
+    batch_worker(&jobs[0]);
+    for (int t = 1; t < n_threads; ++t)
+        if (started[t]) pthread_join(tid[t], NULL);
+    return 0;
+}

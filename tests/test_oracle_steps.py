@@ -1,0 +1,395 @@
+"""Pins for the oracle's individual steps against what the paper fixes.
+
+Each test checks one step of the CPU oracle against data the paper prints
+(the zipper and permute index lists), a quantity that can be computed
+independently (the pi-derived constants), the documented semantics of the
+multiply, closed forms on special states, or the bijectivity that Sec. 6.4
+(Entropy Loss) asserts.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+M64 = (1 << 64) - 1
+
+
+def _read_fields(path):
+    out = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.split()
+    return out
+
+
+@pytest.fixture(scope="module")
+def zipper_printed(golden_dir):
+    return _read_fields(os.path.join(golden_dir, "zipper_printed.txt"))
+
+
+@pytest.fixture(scope="module")
+def permute_printed(golden_dir):
+    return _read_fields(os.path.join(golden_dir, "permute_printed.txt"))
+
+
+def _bytes_le(x, n=8):
+    return [(x >> (8 * j)) & 0xFF for j in range(n)]
+
+
+def _from_le(bs):
+    return sum(int(b) << (8 * j) for j, b in enumerate(bs))
+
+
+def _byte_quality(b):
+    """Sec. 4.1: sum over the byte's bits of the bit's minimum distance from
+    the ends of its 64-bit lane."""
+    return sum(min(k, 63 - k) for k in range(8 * b, 8 * b + 8))
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.1 Zipper Merge
+
+
+def test_byte_quality_ranking_matches_paper(zipper_printed):
+    q = [_byte_quality(b) for b in range(8)]
+    best = [int(x) for x in zipper_printed["best"]]
+    adequate = [int(x) for x in zipper_printed["adequate"]]
+    worst = [int(x) for x in zipper_printed["worst"]]
+    assert min(q[b] for b in best) > max(q[b] for b in adequate)
+    assert min(q[b] for b in adequate) > max(q[b] for b in worst)
+    # "2, 5, 1, 6" is in decreasing order of quality
+    assert [q[b] for b in adequate] == sorted([q[b] for b in adequate], reverse=True)
+
+
+def _perm_high_first(tokens):
+    """Printed list (i=15 first) -> P with P[i] the source byte of result i."""
+    vals = [int(t, 16) for t in tokens]
+    return list(reversed(vals))
+
+
+def _perm_low_first(tokens):
+    return [int(t, 16) for t in tokens]
+
+
+def _requirement1(P):
+    """The worst bytes (0 and 7 of each source lane) land in the upper 32 bits
+    of their result lane."""
+    worst = {0, 7, 8, 15}
+    return all((i % 8) >= 4 for i in range(16) if P[i] in worst)
+
+
+def _requirement2(P):
+    """At most two adjacent result bytes (inside a 32-bit half) come from the
+    same source lane."""
+    for h in range(4):
+        lanes = [P[4 * h + k] // 8 for k in range(4)]
+        run = best = 1
+        for a, b in zip(lanes, lanes[1:]):
+            run = run + 1 if a == b else 1
+            best = max(best, run)
+        if best > 2:
+            return False
+    return True
+
+
+def _low_half_quality(P, lane):
+    return sum(_byte_quality(P[8 * lane + k] % 8) for k in range(4))
+
+
+def test_printed_zipper_satisfies_requirements_high_first(zipper_printed):
+    P = _perm_high_first(zipper_printed["final"])
+    assert sorted(P) == list(range(16))
+    assert _requirement1(P)
+    assert _requirement2(P)
+    # requirement 3: "exactly equal quality in both lanes"
+    assert _low_half_quality(P, 0) == _low_half_quality(P, 1)
+    # the partial permutation agrees on every fixed position
+    partial = list(reversed(zipper_printed["partial"]))
+    for i, t in enumerate(partial):
+        if t != "?":
+            assert P[i] == int(t, 16)
+
+
+def test_low_first_reading_violates_requirement1(zipper_printed):
+    # justifies reading the list with i=15 first
+    assert not _requirement1(_perm_low_first(zipper_printed["final"]))
+
+
+def test_oracle_zipper_applies_printed_permutation(zipper_printed):
+    P = _perm_high_first(zipper_printed["final"])
+    # source bytes S_k = k, so every result byte names its source offset
+    a = _from_le(list(range(0, 8)))
+    b = _from_le(list(range(8, 16)))
+    ra, rb = oracle.zipper_merge(a, b)
+    R = _bytes_le(ra) + _bytes_le(rb)
+    assert R == P
+
+
+def test_oracle_zipper_random_pairs_follow_listing(zipper_printed):
+    P = _perm_high_first(zipper_printed["final"])
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        a, b = (int(x) for x in rng.integers(0, 2**64, size=2, dtype=np.uint64))
+        S = _bytes_le(a) + _bytes_le(b)
+        ra, rb = oracle.zipper_merge(a, b)
+        assert _bytes_le(ra) + _bytes_le(rb) == [S[P[i]] for i in range(16)]
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.3 Permute
+
+
+def test_oracle_permute_applies_printed_indices(permute_printed):
+    idx = [int(t) for t in permute_printed["indices"]]   # highest element first
+    v0 = [((2 * i + 1) << 32) | (2 * i) for i in range(4)]  # element e holds e
+    out = oracle.permute(v0)
+    elems = []
+    for w in out:
+        elems += [w & 0xFFFFFFFF, w >> 32]
+    assert elems == [idx[7 - e] for e in range(8)]
+
+
+def _rot32(x):
+    return ((x >> 32) | (x << 32)) & M64
+
+
+def test_permute_swaps_128bit_halves_and_32bit_halves():
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        v0 = [int(x) for x in rng.integers(0, 2**64, size=4, dtype=np.uint64)]
+        out = oracle.permute(v0)
+        assert out == [_rot32(v0[(i + 2) % 4]) for i in range(4)]
+        assert oracle.permute(out) == v0  # an involution
+
+
+def test_low_first_permute_reading_is_not_a_half_swap(permute_printed):
+    # Read low-first, the indices would give (v[1], v[0], v[3], v[2]) -- the
+    # 128-bit halves would not be swapped, contradicting the text.
+    idx = [int(t) for t in permute_printed["indices"]]
+    elems = list(range(8))
+    dst = [elems[idx[e]] for e in range(8)]
+    lanes = [(dst[2 * i + 1], dst[2 * i]) for i in range(4)]
+    assert lanes[0] == (3, 2)  # = lane 1 unrotated: no swap of 128-bit halves
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.4 constants from the hexadecimal digits of pi
+
+
+def _atan_inv(x, one):
+    """arctan(1/x) * one, by its Taylor series in exact integers."""
+    total = term = one // x
+    x2 = x * x
+    k = 1
+    while term:
+        term //= x2
+        total += (-1) ** k * (term // (2 * k + 1))
+        k += 1
+    return total
+
+
+def _pi_fraction_words(n_words, method="machin"):
+    bits = 64 * n_words + 64
+    if method == "machin":
+        one = 1 << (bits + 32)
+        pi = 16 * _atan_inv(5, one) - 4 * _atan_inv(239, one)
+        pi >>= 32
+    else:
+        import mpmath
+        mpmath.mp.prec = bits + 64
+        pi = int(mpmath.floor(mpmath.pi * mpmath.mpf(2) ** bits))
+    frac = pi & ((1 << bits) - 1)
+    return [(frac >> (bits - 64 * (k + 1))) & M64 for k in range(n_words)]
+
+
+def _fourth_lane(a, b, c):
+    """Bit k set iff zero or one of the three other lanes has bit k set."""
+    at_least_two = (a & b) | (a & c) | (b & c)
+    return ~at_least_two & M64
+
+
+@pytest.mark.parametrize("method", ["machin", "mpmath"])
+def test_constants_follow_pi_derivation(method):
+    if method == "mpmath":
+        pytest.importorskip("mpmath")
+    w = _pi_fraction_words(8, method)
+    assert w[0] == 0x243F6A8885A308D3  # pi = 3.243F6A8885A308D3...
+    c0, c1 = oracle.constants()
+    assert c0[3] == w[0] and c0[2] == w[1] and c0[1] == w[2]
+    assert c1[3] == w[4] and c1[2] == w[5] and c1[1] == w[6]
+    assert c0[0] == _fourth_lane(w[0], w[1], w[2])
+    assert c1[0] == _fourth_lane(w[4], w[5], w[6])
+
+
+def test_constants_set_every_bit_in_some_lane():
+    for c in oracle.constants():
+        for k in range(64):
+            n = sum((lane >> k) & 1 for lane in c)
+            assert 1 <= n <= 3
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.4 Reset
+
+
+def test_reset_expands_key():
+    rng = np.random.default_rng(11)
+    key = [int(x) for x in rng.integers(0, 2**64, size=4, dtype=np.uint64)]
+    c0, c1 = oracle.constants()
+    s = [int(x) for x in oracle.reset(key)]
+    v0, v1, mul0, mul1 = s[0:4], s[4:8], s[8:12], s[12:16]
+    assert mul0 == c0 and mul1 == c1
+    assert v0 == [key[i] ^ c0[i] for i in range(4)]
+    assert v1 == [_rot32(key[i]) ^ c1[i] for i in range(4)]
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.2 Update
+
+
+def _state(v0, v1, mul0, mul1):
+    return np.array(list(v0) + list(v1) + list(mul0) + list(mul1), dtype=np.uint64)
+
+
+def _split(s):
+    s = [int(x) for x in s]
+    return s[0:4], s[4:8], s[8:12], s[12:16]
+
+
+def _zm_vec(v):
+    a = oracle.zipper_merge(v[0], v[1])
+    b = oracle.zipper_merge(v[2], v[3])
+    return [a[0], a[1], b[0], b[1]]
+
+
+def test_update_on_zero_state_closed_form():
+    # With v0 = v1 = mul0 = mul1 = 0 both products vanish, so
+    # v0 = ZM(p) and v1 = p + ZM(ZM(p)).
+    rng = np.random.default_rng(5)
+    p = [int(x) for x in rng.integers(0, 2**64, size=4, dtype=np.uint64)]
+    v0, v1, mul0, mul1 = _split(oracle.update(np.zeros(16, np.uint64), p))
+    zp = _zm_vec(p)
+    assert mul0 == [0] * 4 and mul1 == [0] * 4
+    assert v0 == zp
+    assert v1 == [(p[i] + z) & M64 for i, z in enumerate(_zm_vec(zp))]
+
+
+def test_update_multiply_uses_low_v1_times_high_v0():
+    # v0 = 2^32 (hi=1, lo=0), v1 = mul0 = mul1 = 0: mul0 becomes lo32(p) and
+    # mul1 stays 0 (its product has the factor lo32(v0) = 0).  Transposed
+    # operands would leave mul0 at 0.
+    p = [0x0123456789ABCDEF, 0xFEDCBA9876543210, 0x1111111122222222, 0xDEADBEEFCAFEBABE]
+    s = _state([1 << 32] * 4, [0] * 4, [0] * 4, [0] * 4)
+    _, _, mul0, mul1 = _split(oracle.update(s, p))
+    assert mul0 == [x & 0xFFFFFFFF for x in p]
+    assert mul1 == [0] * 4
+
+
+def test_update_second_multiply_after_adding_mul1():
+    # v0 = A (hi 0), v1 = 0, mul0 = 0, mul1 = M: the first product is 0; v0
+    # becomes A + M and mul1 becomes M ^ lo32(A + M) * hi32(p).
+    A = [0x9ABCDEF0, 0x13579BDF, 0x2468ACE0, 0x0F1E2D3C]
+    M = [0x0102030405060708, 0xA1B2C3D4E5F60718, 0x1, 0xFFFFFFFF00000000]
+    p = [0x1111111122222222, 0x3333333344444444, 0xFFFFFFFFFFFFFFFF, 0x8000000000000001]
+    s = _state(A, [0] * 4, [0] * 4, M)
+    _, _, mul0, mul1 = _split(oracle.update(s, p))
+    assert mul0 == [0] * 4
+    for i in range(4):
+        t = (A[i] + M[i]) & M64
+        assert mul1[i] == M[i] ^ ((t & 0xFFFFFFFF) * (p[i] >> 32))
+
+
+def _inverse_update(s, p):
+    """Undo one Update for a known packet (Sec. 6.4: Update is a
+    permutation of the state for a fixed packet)."""
+    v0, v1, mul0, mul1 = _split(s)
+    v1 = [(v1[i] - z) & M64 for i, z in enumerate(_zm_vec(v0))]
+    v0 = [(v0[i] - z) & M64 for i, z in enumerate(_zm_vec(v1))]
+    mul1 = [mul1[i] ^ ((v0[i] & 0xFFFFFFFF) * (v1[i] >> 32)) for i in range(4)]
+    v0 = [(v0[i] - mul1[i]) & M64 for i in range(4)]
+    mul0 = [mul0[i] ^ ((v1[i] & 0xFFFFFFFF) * (v0[i] >> 32)) for i in range(4)]
+    v1 = [(v1[i] - mul0[i] - p[i]) & M64 for i in range(4)]
+    return _state(v0, v1, mul0, mul1)
+
+
+def test_update_is_a_bijection_round_trip():
+    rng = np.random.default_rng(13)
+    for _ in range(300):
+        s = rng.integers(0, 2**64, size=16, dtype=np.uint64)
+        p = [int(x) for x in rng.integers(0, 2**64, size=4, dtype=np.uint64)]
+        t = oracle.update(s, p)
+        assert not np.array_equal(t, s)
+        assert np.array_equal(_inverse_update(t, p), s)
+
+
+def test_update_lanes_pairwise_independent():
+    # ZipperMerge only combines adjacent lanes (Sec. 4.3): changing lane 2 or
+    # 3 of the state or packet leaves lanes 0 and 1 of one Update unchanged.
+    rng = np.random.default_rng(17)
+    for _ in range(50):
+        s = rng.integers(0, 2**64, size=16, dtype=np.uint64)
+        p = [int(x) for x in rng.integers(0, 2**64, size=4, dtype=np.uint64)]
+        p2 = list(p)
+        p2[3] ^= 1 << int(rng.integers(0, 64))
+        a, b = oracle.update(s, p), oracle.update(s, p2)
+        for base in (0, 4, 8, 12):
+            assert a[base] == b[base] and a[base + 1] == b[base + 1]
+        assert not np.array_equal(a, b)
+
+
+# --------------------------------------------------------------------------
+# Sec. 4.5 remainder, Sec. 4.3 finalization: conformance to the stated readings
+
+
+def _rotl32(x, r):
+    return ((x << r) | (x >> (32 - r))) & 0xFFFFFFFF
+
+
+def test_remainder_follows_documented_reading():
+    rng = np.random.default_rng(19)
+    for r in range(1, 32):
+        s = rng.integers(0, 2**64, size=16, dtype=np.uint64)
+        tail = rng.integers(0, 256, size=r, dtype=np.uint8)
+        v0, v1, mul0, mul1 = _split(s)
+        v0 = [(x + r * ((1 << 32) + 1)) & M64 for x in v0]
+        v1 = [(_rotl32(x >> 32, r) << 32) | _rotl32(x & 0xFFFFFFFF, r) for x in v1]
+        q, m = r - r % 4, r % 4
+        P = [0] * 32
+        P[:q] = [int(b) for b in tail[:q]]
+        P[28:28 + m] = [int(b) for b in tail[q:q + m]]
+        packet = [_from_le(P[8 * i:8 * i + 8]) for i in range(4)]
+        want = oracle.update(_state(v0, v1, mul0, mul1), packet)
+        assert np.array_equal(oracle.remainder(s, tail), want)
+
+
+def test_no_remainder_step_for_multiples_of_32():
+    # Sec. 5: a size that is a multiple of 32 "requires no padding"
+    rng = np.random.default_rng(23)
+    key = [int(x) for x in rng.integers(0, 2**64, size=4, dtype=np.uint64)]
+    for n_packets in (0, 1, 3):
+        msg = rng.integers(0, 256, size=32 * n_packets, dtype=np.uint8)
+        s = oracle.reset(key)
+        for t in range(n_packets):
+            s = oracle.update(s, [_from_le(list(msg[32 * t + 8 * i:32 * t + 8 * i + 8]))
+                                  for i in range(4)])
+        _, out = oracle.finalize(s)
+        assert oracle.hash_words(key, msg, 4) == out
+
+
+def test_finalize_is_four_permute_updates_then_sum():
+    rng = np.random.default_rng(29)
+    s = rng.integers(0, 2**64, size=16, dtype=np.uint64)
+    t = s.copy()
+    for _ in range(4):
+        v0 = [int(x) for x in t[0:4]]
+        t = oracle.update(t, oracle.permute(v0))
+    v0, v1, mul0, mul1 = _split(t)
+    want = [(v0[i] + v1[i] + mul0[i] + mul1[i]) & M64 for i in range(4)]
+    s2, got = oracle.finalize(s)
+    assert got == want and np.array_equal(s2, t)
