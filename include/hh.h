@@ -1,0 +1,157 @@
+/*
+ * hh.h -- C ABI of libhh.so: batched HighwayHash on AMD Instinct MI355X (gfx950).
+ *
+ * HighwayHash is the keyed hash / pseudo-random function of "Fast keyed
+ * hash/pseudo-random function using SIMD multiply and permute" (Alakuijala,
+ * Cox, Wassenberg; arXiv:1612.06257).  A 256-bit key and a byte string of any
+ * length (including 0) give a 64-, 128- or 256-bit result (Sec. 1 and 4.3):
+ *   Reset(key) (Sec. 4.4); Update(packet) for every full 32-byte packet
+ *   (Sec. 4.1, 4.2); if size mod 32 != 0, the size-injected, v1-rotated padded
+ *   remainder packet (Sec. 4.5); four rounds of Update(Permute(v0)) and the
+ *   sum v0 + v1 + mul0 + mul1 of the four state vectors (Sec. 4.3).
+ * The 64-bit hash is lane 0 of that sum, the 128-bit hash lanes 0..1 and the
+ * 256-bit hash lanes 0..3.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named in the argument list are DEVICE pointers unless noted.
+ *     The caller owns every buffer and keeps it alive until the work enqueued
+ *     on `stream` has finished; the library keeps no reference after return.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls only enqueue work; results are visible after stream or event
+ *     synchronisation.
+ *   - A key is four uint64 words; word i is lane i (a 32-byte key read
+ *     little-endian).  keys[4*k + i] is lane i of key k.
+ *   - Message j is data[offsets[j] .. offsets[j] + lengths[j]), bytes at any
+ *     alignment; offsets[j] + lengths[j] <= data_bytes is the caller's
+ *     contract.  The kernels never read outside [data, data + data_bytes)
+ *     rounded out to whole 4-byte words: a message that violates the contract
+ *     is clamped to the buffer and hashed truncated, it never faults.
+ *   - key_idx[j] selects message j's key; NULL means key 0 for every message.
+ *     An index >= n_keys is clamped to n_keys - 1.
+ *   - Outputs are uint64 words, message-major, lane 0 first:
+ *     out[w*j + i] is word i of message j's w-word hash.
+ *   - `out` must not overlap any input.  n_msgs == 0 is a valid no-op.
+ *   - Argument errors are reported synchronously (HH_ERR_INVALID_ARG) before
+ *     any device call.  A device that is not gfx950 gives
+ *     HH_ERR_UNSUPPORTED_DEVICE.  Faults of enqueued work surface at stream
+ *     synchronisation.
+ */
+#ifndef HH_H_
+#define HH_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HH_OK = 0,
+    HH_ERR_INVALID_ARG = 1,
+    HH_ERR_UNSUPPORTED_DEVICE = 2,
+    HH_ERR_OUT_OF_MEMORY = 3,
+    HH_ERR_LAUNCH = 4
+} hh_status;
+
+/* Human-readable text for a status code (static storage, never NULL). */
+const char* hh_status_string(hh_status status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int hh_version(void);
+
+/* The two initialization constants of Sec. 4.4 (host pointers, 4 words each,
+ * lane 0 first), as the kernels use them. */
+void hh_get_constants(uint64_t c0[4], uint64_t c1[4]);
+
+/* Batched one-shot hashing (Sec. 4.2-4.5), 64-, 128- or 256-bit results.
+ * The library picks the kernel: a planner buckets messages by length
+ * (longest first) and a persistent kernel hashes long messages with four
+ * threads per message and short ones with one thread per message. */
+hh_status hh_hash64(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                    const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                    const uint64_t* lengths, uint64_t n_msgs, uint64_t* out, void* stream);
+hh_status hh_hash128(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                     const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                     const uint64_t* lengths, uint64_t n_msgs, uint64_t* out, void* stream);
+hh_status hh_hash256(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                     const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                     const uint64_t* lengths, uint64_t n_msgs, uint64_t* out, void* stream);
+
+/* Explicit kernel choice, same arguments plus the output width in words
+ * (1, 2 or 4).  The result never depends on the path:
+ *   HH_PATH_AUTO        what hh_hash64/128/256 do;
+ *   HH_PATH_LANE1       one launch, one thread per message (all 4 lanes in
+ *                       registers), messages in index order;
+ *   HH_PATH_LANE4       one launch, four threads per message (one lane each,
+ *                       DPP exchanges), messages in index order;
+ *   HH_PATH_BUCKETED    length planner + persistent kernel (the AUTO path). */
+typedef enum {
+    HH_PATH_AUTO = 0,
+    HH_PATH_LANE1 = 1,
+    HH_PATH_LANE4 = 2,
+    HH_PATH_BUCKETED = 3
+} hh_path;
+
+hh_status hh_hash_path(hh_path path, uint32_t width_words, const uint64_t* keys,
+                       uint32_t n_keys, const uint32_t* key_idx, const uint8_t* data,
+                       uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
+                       uint64_t n_msgs, uint64_t* out, void* stream);
+
+/* The "plain" kernel: every message has the same `length`, one thread per
+ * message, one launch.  Hashing a batch of mixed lengths with it takes one
+ * call per distinct length (the baseline the batched path is measured
+ * against).  64-bit results. */
+hh_status hh_hash64_uniform(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                            const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                            uint64_t length, uint64_t n_msgs, uint64_t* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Incremental hashing (Sec. 4.5: only size mod 32 enters the hash, so a stream
+ * is fully described by the 1024-bit state once whole packets are consumed).
+ * A state is HH_STATE_WORDS uint64 words in device memory, caller-owned:
+ * v0[0..3], v1[0..3], mul0[0..3], mul1[0..3].
+ */
+#define HH_STATE_WORDS 16
+
+/* states[16*s ..] = Reset(keys[key_idx[s]]) for s < n (key_idx NULL: key 0). */
+hh_status hh_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                        uint64_t* states, uint64_t n, void* stream);
+
+/* Item k folds data[offsets[k] .. + lengths[k]) into state state_idx[k]
+ * (state_idx NULL: state k).  Every lengths[k] must be a multiple of 32
+ * (HH_ERR_INVALID_ARG is not checked on the device: a length that is not is
+ * rounded down).  Two items must not name the same state in one call. */
+hh_status hh_state_update(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
+                          uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
+                          uint64_t n, void* stream);
+
+/* Item k folds its bytes (any length: whole packets, then the remainder
+ * step with r = lengths[k] mod 32, which must equal the stream's total size
+ * mod 32) into state state_idx[k], finalizes and writes width_words[k]
+ * (1, 2 or 4; NULL = 1) words to out[out_offsets[k] ..] (out_offsets NULL:
+ * out[4*k ..]).  The state is left finalized (not reusable). */
+hh_status hh_state_final(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
+                         uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
+                         const uint8_t* width_words, uint64_t* out, const uint64_t* out_offsets,
+                         uint64_t n, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Tuning of the bucketed path (host-side settings, process-wide). */
+typedef struct {
+    uint32_t lane4_min_bytes;   /* messages at least this long use 4 threads each */
+    uint32_t waves_per_cu;      /* persistent grid: CUs x waves_per_cu waves */
+    uint32_t use_graph;         /* capture planner + hash launches in a hipGraph */
+    uint32_t reserved;
+} hh_tuning;
+
+void hh_get_tuning(hh_tuning* t);
+hh_status hh_set_tuning(const hh_tuning* t);
+
+/* Free the library's per-device workspaces and cached graphs. */
+hh_status hh_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HH_H_ */

@@ -1,0 +1,185 @@
+// hh_api.hip -- the C ABI declared in include/hh.h: argument checks, device
+// checks and dispatch to the kernel launchers.
+
+#include <mutex>
+#include <string.h>
+
+#include "hh_device.hpp"
+#include "hh_internal.hpp"
+
+namespace hh {
+
+namespace {
+
+std::mutex g_mutex;
+constexpr int kMaxDevices = 64;
+signed char g_device_ok[kMaxDevices];  // 0 unknown, 1 gfx950, -1 other
+hh_tuning g_tuning = {4096u, 8u, 1u, 0u};
+
+hh_status check_hash_args(const HashArgs& a) {
+    if (a.n == 0) return HH_OK;
+    if (!a.keys || a.n_keys == 0 || !a.offsets || !a.lengths || !a.out) return HH_ERR_INVALID_ARG;
+    if (!a.data && a.data_bytes != 0) return HH_ERR_INVALID_ARG;
+    if (a.width != 1 && a.width != 2 && a.width != 4) return HH_ERR_INVALID_ARG;
+    return HH_OK;
+}
+
+}  // namespace
+
+hh_status check_device(int* device_out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return HH_ERR_UNSUPPORTED_DEVICE;
+    }
+    if (device_out) *device_out = dev;
+    if (dev < kMaxDevices && g_device_ok[dev] != 0) {
+        return g_device_ok[dev] > 0 ? HH_OK : HH_ERR_UNSUPPORTED_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return HH_ERR_UNSUPPORTED_DEVICE;
+    }
+    const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (dev < kMaxDevices) g_device_ok[dev] = ok ? 1 : -1;
+    return ok ? HH_OK : HH_ERR_UNSUPPORTED_DEVICE;
+}
+
+hh_tuning current_tuning() {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    return g_tuning;
+}
+
+static hh_status hash_dispatch(hh_path path, const HashArgs& a, void* stream) {
+    hh_status s = check_hash_args(a);
+    if (s != HH_OK || a.n == 0) return s;
+    if ((s = check_device(nullptr)) != HH_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    switch (path) {
+        case HH_PATH_LANE1: return launch_thread(a, 0, st);
+        case HH_PATH_LANE4: return launch_quad(a, st);
+        case HH_PATH_AUTO:
+        case HH_PATH_BUCKETED: return launch_bucketed(a, st);
+        default: return HH_ERR_INVALID_ARG;
+    }
+}
+
+}  // namespace hh
+
+using hh::HashArgs;
+
+extern "C" {
+
+const char* hh_status_string(hh_status status) {
+    switch (status) {
+        case HH_OK: return "ok";
+        case HH_ERR_INVALID_ARG: return "invalid argument";
+        case HH_ERR_UNSUPPORTED_DEVICE: return "no gfx950 device is current";
+        case HH_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case HH_ERR_LAUNCH: return "kernel launch failed";
+    }
+    return "unknown status";
+}
+
+int hh_version(void) { return 100; }
+
+void hh_get_constants(uint64_t c0[4], uint64_t c1[4]) {
+    for (int i = 0; i < 4; ++i) {
+        c0[i] = hh::init0(i);
+        c1[i] = hh::init1(i);
+    }
+}
+
+hh_status hh_hash_path(hh_path path, uint32_t width_words, const uint64_t* keys, uint32_t n_keys,
+                       const uint32_t* key_idx, const uint8_t* data, uint64_t data_bytes,
+                       const uint64_t* offsets, const uint64_t* lengths, uint64_t n_msgs,
+                       uint64_t* out, void* stream) {
+    const HashArgs a{keys, n_keys, key_idx, data, data_bytes, offsets, lengths, n_msgs, out,
+                     width_words};
+    return hh::hash_dispatch(path, a, stream);
+}
+
+hh_status hh_hash64(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                    const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                    const uint64_t* lengths, uint64_t n_msgs, uint64_t* out, void* stream) {
+    return hh_hash_path(HH_PATH_AUTO, 1, keys, n_keys, key_idx, data, data_bytes, offsets, lengths,
+                        n_msgs, out, stream);
+}
+
+hh_status hh_hash128(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                     const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                     const uint64_t* lengths, uint64_t n_msgs, uint64_t* out, void* stream) {
+    return hh_hash_path(HH_PATH_AUTO, 2, keys, n_keys, key_idx, data, data_bytes, offsets, lengths,
+                        n_msgs, out, stream);
+}
+
+hh_status hh_hash256(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                     const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                     const uint64_t* lengths, uint64_t n_msgs, uint64_t* out, void* stream) {
+    return hh_hash_path(HH_PATH_AUTO, 4, keys, n_keys, key_idx, data, data_bytes, offsets, lengths,
+                        n_msgs, out, stream);
+}
+
+hh_status hh_hash64_uniform(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                            const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                            uint64_t length, uint64_t n_msgs, uint64_t* out, void* stream) {
+    if (n_msgs == 0) return HH_OK;
+    if (!keys || n_keys == 0 || !offsets || !out || (!data && data_bytes != 0))
+        return HH_ERR_INVALID_ARG;
+    hh_status s = hh::check_device(nullptr);
+    if (s != HH_OK) return s;
+    const HashArgs a{keys, n_keys, key_idx, data, data_bytes, offsets, nullptr, n_msgs, out, 1};
+    return hh::launch_thread(a, length, (hipStream_t)stream);
+}
+
+hh_status hh_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                        uint64_t* states, uint64_t n, void* stream) {
+    if (n == 0) return HH_OK;
+    if (!keys || n_keys == 0 || !states) return HH_ERR_INVALID_ARG;
+    hh_status s = hh::check_device(nullptr);
+    if (s != HH_OK) return s;
+    return hh::launch_state_init(keys, n_keys, key_idx, states, n, (hipStream_t)stream);
+}
+
+hh_status hh_state_update(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
+                          uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
+                          uint64_t n, void* stream) {
+    if (n == 0) return HH_OK;
+    if (!states || !offsets || !lengths || (!data && data_bytes != 0)) return HH_ERR_INVALID_ARG;
+    hh_status s = hh::check_device(nullptr);
+    if (s != HH_OK) return s;
+    return hh::launch_state_step(false, states, state_idx, data, data_bytes, offsets, lengths,
+                                 nullptr, nullptr, nullptr, n, (hipStream_t)stream);
+}
+
+hh_status hh_state_final(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
+                         uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
+                         const uint8_t* width_words, uint64_t* out, const uint64_t* out_offsets,
+                         uint64_t n, void* stream) {
+    if (n == 0) return HH_OK;
+    if (!states || !offsets || !lengths || !out || (!data && data_bytes != 0))
+        return HH_ERR_INVALID_ARG;
+    hh_status s = hh::check_device(nullptr);
+    if (s != HH_OK) return s;
+    return hh::launch_state_step(true, states, state_idx, data, data_bytes, offsets, lengths,
+                                 width_words, out, out_offsets, n, (hipStream_t)stream);
+}
+
+void hh_get_tuning(hh_tuning* t) {
+    if (t) *t = hh::current_tuning();
+}
+
+hh_status hh_set_tuning(const hh_tuning* t) {
+    if (!t || t->waves_per_cu == 0 || t->waves_per_cu > 32) return HH_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(hh::g_mutex);
+    hh::g_tuning = *t;
+    return HH_OK;
+}
+
+hh_status hh_release(void) {
+    hh::release_bucketed();
+    return HH_OK;
+}
+
+}  // extern "C"

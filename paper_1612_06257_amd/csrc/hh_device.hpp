@@ -1,0 +1,362 @@
+// hh_device.hpp -- HighwayHash device primitives for gfx950 (CDNA4, wave64).
+//
+// Two register layouts of the 1024-bit state (Sec. 4.2: v0, v1, mul0, mul1,
+// each four independent 64-bit lanes):
+//
+//   Lanes4 (one thread per message): a thread holds all 16 words.  ZipperMerge
+//     and Permute are pure register renaming plus v_perm_b32; no exchange.
+//   Lane1 (four threads per message, "quad"): thread q of a quad (q = lane id
+//     mod 4) holds lane q of each vector, 4 words.  ZipperMerge of the pair
+//     (0,1) / (2,3) needs only the partner's HIGH dword (one DPP move);
+//     Permute needs lane q^2's v0 (two DPP moves).
+//
+// 64-bit adds compile to v_lshl_add_u64, the 32x32->64 products of
+// _mm256_mul_epu32 to v_mad_u64_u32, byte permutes to v_perm_b32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hh {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef uint8_t u8;
+
+// ---------------------------------------------------------------------------
+// Sec. 4.4 initialization constants.  Lanes 3, 2, 1 of the first constant are
+// the first three 64-bit words of the hexadecimal fraction of pi, lanes 3, 2,
+// 1 of the second the fifth to seventh words; lane 0 of each is rebuilt so
+// that a bit is set there exactly when zero or one of the other lanes set it.
+constexpr u64 kPiWord0 = 0x243f6a8885a308d3ull;
+constexpr u64 kPiWord1 = 0x13198a2e03707344ull;
+constexpr u64 kPiWord2 = 0xa4093822299f31d0ull;
+constexpr u64 kPiWord4 = 0x452821e638d01377ull;
+constexpr u64 kPiWord5 = 0xbe5466cf34e90c6cull;
+constexpr u64 kPiWord6 = 0xc0ac29b7c97c50ddull;
+
+constexpr u64 rebuilt_lane(u64 a, u64 b, u64 c) { return ~((a & b) | (a & c) | (b & c)); }
+
+constexpr u64 kInit0Lane0 = rebuilt_lane(kPiWord0, kPiWord1, kPiWord2);
+constexpr u64 kInit1Lane0 = rebuilt_lane(kPiWord4, kPiWord5, kPiWord6);
+
+__host__ __device__ constexpr u64 init0(int lane) {
+    return lane == 0 ? kInit0Lane0 : lane == 1 ? kPiWord2 : lane == 2 ? kPiWord1 : kPiWord0;
+}
+__host__ __device__ constexpr u64 init1(int lane) {
+    return lane == 0 ? kInit1Lane0 : lane == 1 ? kPiWord6 : lane == 2 ? kPiWord5 : kPiWord4;
+}
+
+// ---------------------------------------------------------------------------
+// scalar helpers
+
+__device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
+__device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
+// (hi:lo) as one 64-bit value; a vector bitcast rather than shift/or keeps
+// the compiler from splitting later 64-bit adds of it into 32-bit pieces
+__device__ __forceinline__ u64 make64(u32 lo, u32 hi) {
+    const u32x2 v = {lo, hi};
+    return __builtin_bit_cast(u64, v);
+}
+__device__ __forceinline__ u64 rot32(u64 x) { return make64(hi32(x), lo32(x)); }
+
+// 32x32 -> 64 product of the low halves (_mm256_mul_epu32), v_mad_u64_u32
+__device__ __forceinline__ u64 mul_lo_hi(u64 x, u64 y) { return (u64)lo32(x) * (u64)hi32(y); }
+
+// v_perm_b32: result byte k = byte sel[k] of the 8-byte value (a:b), where
+// selector values 0..3 name bytes of b and 4..7 bytes of a; 0x0c gives 0.
+__device__ __forceinline__ u32 perm(u32 a, u32 b, u32 sel) {
+    return __builtin_amdgcn_perm(a, b, sel);
+}
+
+// (hi:lo) >> 8*sh, low 32 bits (v_alignbyte_b32); sh in 0..3
+__device__ __forceinline__ u32 align_bytes(u32 hi, u32 lo, u32 sh) {
+    return __builtin_amdgcn_alignbyte(hi, lo, sh);
+}
+
+// rotate each 32-bit half of x left by r, 1 <= r <= 31 (v_alignbit_b32)
+__device__ __forceinline__ u64 rotl_halves(u64 x, u32 r) {
+    u32 l = lo32(x), h = hi32(x);
+    return make64(__builtin_amdgcn_alignbit(l, l, 32u - r), __builtin_amdgcn_alignbit(h, h, 32u - r));
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 4.1 ZipperMerge of one 16-byte lane pair (a = lane 2k, b = lane 2k+1).
+// Result bytes R_i = S_{P_i} with P (low byte first) =
+//   3 12 2 5 | 14 1 15 0 | 11 4 10 13 | 9 6 8 7
+// In dwords (a = al:ah, b = bl:bh):
+//   R[0..3]   = al.3 bh.0 al.2 ah.1      R[4..7]   = bh.2 al.1 bh.3 al.0
+//   R[8..11]  = bl.3 ah.0 bl.2 bh.1      R[12..15] = bl.1 ah.2 bl.0 ah.3
+// Five v_perm_b32: m gathers the four bytes of ah/bh that the two
+// three-source dwords need.
+__device__ __forceinline__ void zipper_pair(u64 a, u64 b, u64& ra, u64& rb) {
+    const u32 al = lo32(a), ah = hi32(a), bl = lo32(b), bh = hi32(b);
+    const u32 m = perm(ah, bh, 0x05040100u);   // bh.0 bh.1 ah.0 ah.1
+    const u32 r0 = perm(m, al, 0x07020403u);   // al.3 m.0 al.2 m.3
+    const u32 r1 = perm(bh, al, 0x00070106u);  // bh.2 al.1 bh.3 al.0
+    const u32 r2 = perm(m, bl, 0x05020603u);   // bl.3 m.2 bl.2 m.1
+    const u32 r3 = perm(ah, bl, 0x07000601u);  // bl.1 ah.2 bl.0 ah.3
+    ra = make64(r0, r1);
+    rb = make64(r2, r3);
+}
+
+// ---------------------------------------------------------------------------
+// Lanes4 layout: the whole state in one thread.
+
+struct State4 {
+    u64 v0[4], v1[4], mul0[4], mul1[4];
+};
+
+__device__ __forceinline__ void reset4(State4& s, const u64 key[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        s.mul0[i] = init0(i);
+        s.mul1[i] = init1(i);
+        s.v0[i] = key[i] ^ init0(i);
+        s.v1[i] = rot32(key[i]) ^ init1(i);
+    }
+}
+
+__device__ __forceinline__ void update4(State4& s, const u64 p[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        s.v1[i] += p[i] + s.mul0[i];
+        s.mul0[i] ^= mul_lo_hi(s.v1[i], s.v0[i]);
+        s.v0[i] += s.mul1[i];
+        s.mul1[i] ^= mul_lo_hi(s.v0[i], s.v1[i]);
+    }
+    u64 z[4];
+    zipper_pair(s.v1[0], s.v1[1], z[0], z[1]);
+    zipper_pair(s.v1[2], s.v1[3], z[2], z[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s.v0[i] += z[i];
+    zipper_pair(s.v0[0], s.v0[1], z[0], z[1]);
+    zipper_pair(s.v0[2], s.v0[3], z[2], z[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s.v1[i] += z[i];
+}
+
+// Sec. 4.3: four rounds of Update(Permute(v0)); Permute(v0)[i] = rot32(v0[i^2]).
+__device__ __forceinline__ void finalize4(State4& s, u64 sum[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const u64 p[4] = {rot32(s.v0[2]), rot32(s.v0[3]), rot32(s.v0[0]), rot32(s.v0[1])};
+        update4(s, p);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sum[i] = s.v0[i] + s.v1[i] + s.mul0[i] + s.mul1[i];
+}
+
+// ---------------------------------------------------------------------------
+// Lane1 layout: thread q of a quad holds lane q.  All four threads of a quad
+// must be active whenever these run.
+
+// DPP quad_perm controls
+constexpr int kQuadSwap1 = 0xB1;  // [1,0,3,2]: partner in the zipper pair
+constexpr int kQuadSwap2 = 0x4E;  // [2,3,0,1]: lane q^2 (Permute)
+
+__device__ __forceinline__ u32 quad_swap1(u32 x) {
+    return (u32)__builtin_amdgcn_mov_dpp((int)x, kQuadSwap1, 0xF, 0xF, true);
+}
+__device__ __forceinline__ u32 quad_swap2(u32 x) {
+    return (u32)__builtin_amdgcn_mov_dpp((int)x, kQuadSwap2, 0xF, 0xF, true);
+}
+
+struct State1 {
+    u64 v0, v1, mul0, mul1;
+    u32 sel_hi;  // v_perm selector of this lane's upper result dword
+};
+
+// Zipper result for this thread's lane: own dwords (L, H), partner's H = P.
+//   even lane: lo = L.3 P.0 L.2 H.1   hi = P.2 L.1 P.3 L.0
+//   odd lane:  lo = L.3 P.0 L.2 H.1   hi = L.1 P.2 L.0 P.3
+__device__ __forceinline__ u64 zipper1(u64 x, u32 sel_hi) {
+    const u32 L = lo32(x), H = hi32(x);
+    const u32 P = quad_swap1(H);
+    const u32 m = perm(P, H, 0x0c0c0104u);    // P.0 H.1 0 0
+    const u32 lo = perm(m, L, 0x05020403u);   // L.3 m.0 L.2 m.1
+    const u32 hi = perm(P, L, sel_hi);
+    return make64(lo, hi);
+}
+
+__device__ __forceinline__ void reset1(State1& s, u64 key, int q) {
+    s.mul0 = init0(q);
+    s.mul1 = init1(q);
+    s.v0 = key ^ s.mul0;
+    s.v1 = rot32(key) ^ s.mul1;
+    s.sel_hi = (q & 1) ? 0x07000601u : 0x00070106u;
+}
+
+__device__ __forceinline__ void update1(State1& s, u64 p) {
+    s.v1 += p + s.mul0;
+    s.mul0 ^= mul_lo_hi(s.v1, s.v0);
+    s.v0 += s.mul1;
+    s.mul1 ^= mul_lo_hi(s.v0, s.v1);
+    s.v0 += zipper1(s.v1, s.sel_hi);
+    s.v1 += zipper1(s.v0, s.sel_hi);
+}
+
+__device__ __forceinline__ u64 finalize1(State1& s) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        // Permute: lane q takes rot32 of lane q^2 of v0
+        const u64 p = make64(quad_swap2(hi32(s.v0)), quad_swap2(lo32(s.v0)));
+        update1(s, p);
+    }
+    return s.v0 + s.v1 + s.mul0 + s.mul1;
+}
+
+// ---------------------------------------------------------------------------
+// Loads.  Messages start at any byte; every load reads whole aligned dwords
+// and only dwords that contain at least one byte of the message, so no load
+// leaves the caller's buffer by more than the rest of its last dword (never
+// another page).  Pointers keep their provenance (no integer round trip) so
+// that the loads stay global_load.
+
+__device__ __forceinline__ u32 misalignment(const u8* p) { return (u32)((uintptr_t)p & 3u); }
+
+// Little-endian word of the n (0..4) bytes at p; bytes past n read as 0.
+__device__ __forceinline__ u32 load_partial_le32(const u8* p, u32 n) {
+    if (n == 0) return 0u;
+    const u32 sh = misalignment(p);
+    const u32* d = (const u32*)(p - sh);
+    const u32 d0 = d[0];
+    const u32 d1 = (sh + n > 4u) ? d[1] : 0u;
+    const u32 w = align_bytes(d1, d0, sh);
+    return n >= 4u ? w : (w & ((1u << (8u * n)) - 1u));
+}
+
+// Sec. 4.5 padded remainder packet, dword k (0..7), for the r (1..31) tail
+// bytes at t: the first q = r - r%4 bytes fill packet bytes 0..q-1, the last
+// r%4 bytes go to packet bytes 28..30 (in order); all other bytes are zero.
+__device__ __forceinline__ u32 remainder_dword(const u8* t, u32 r, u32 k) {
+    const u32 q4 = r >> 2;  // whole 4-byte groups
+    if (k < 7u) return k < q4 ? load_partial_le32(t + 4u * k, 4u) : 0u;
+    return load_partial_le32(t + 4u * q4, r & 3u);
+}
+
+// Three aligned dwords covering one lane's 8 packet bytes.  `safe` selects
+// the third dword only when the bytes are misaligned (sh != 0), which keeps
+// the last packet's loads inside the message; otherwise dwords 0..2 are read
+// as one dwordx3 (the third then belongs to the following packet bytes).
+struct Dw3 {
+    u32 x, y, z;
+};
+
+__device__ __forceinline__ Dw3 load_dw3(const u32* d) {
+    Dw3 r;
+    r.x = d[0];
+    r.y = d[1];
+    r.z = d[2];
+    return r;
+}
+
+__device__ __forceinline__ Dw3 load_dw3_safe(const u32* d, u32 sh) {
+    Dw3 r;
+    r.x = d[0];
+    r.y = d[1];
+    r.z = d[sh ? 2 : 1];
+    return r;
+}
+
+__device__ __forceinline__ u64 lane_word(const Dw3& w, u32 sh) {
+    return make64(align_bytes(w.y, w.x, sh), align_bytes(w.z, w.y, sh));
+}
+
+// Quad layout: absorb npk (>= 1) whole packets starting at the lane's bytes
+// lp (= message + 8q + 32*first).  A ring of D packets is kept in flight:
+// packet t+D is requested right after packet t is consumed.  All threads of
+// a quad run with the same npk.
+template <int D>
+__device__ __forceinline__ void absorb_quad(State1& s, const u8* lp, u32 npk) {
+    const u32 sh = misalignment(lp);
+    const u32* d = (const u32*)(lp - sh);
+    const u32 last = npk - 1u;
+    Dw3 ring[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ring[k] = load_dw3_safe(d + 8u * min((u32)k, last), sh);
+    u32 t0 = 0;
+    // steady state: every requested packet is at most the second to last,
+    // so dwords 0..2 are inside the message
+    for (; t0 + 2u * D < npk; t0 += D) {
+        const u32* blk = d + 8u * (t0 + D);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            update1(s, lane_word(ring[k], sh));
+            ring[k] = load_dw3(blk + 8 * k);
+        }
+    }
+    // drain: fewer than 2D packets remain
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (t0 + k < npk) {
+            update1(s, lane_word(ring[k], sh));
+            ring[k] = load_dw3_safe(d + 8u * min(t0 + D + k, last), sh);
+        }
+    }
+    t0 += D;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        if (t0 + k < npk) update1(s, lane_word(ring[k], sh));
+}
+
+// Thread layout: 32 packet bytes at p as nine aligned dwords (the ninth only
+// read when p is misaligned).
+struct Dw9 {
+    u32 w[9];
+};
+
+__device__ __forceinline__ Dw9 load_dw9(const u32* d, u32 sh, bool safe) {
+    Dw9 r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r.w[k] = d[k];
+    r.w[8] = safe ? d[sh ? 8 : 7] : d[8];
+    return r;
+}
+
+__device__ __forceinline__ void packet_words(const Dw9& r, u32 sh, u64 pk[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        pk[i] = make64(align_bytes(r.w[2 * i + 1], r.w[2 * i], sh),
+                       align_bytes(r.w[2 * i + 2], r.w[2 * i + 1], sh));
+}
+
+template <int D>
+__device__ __forceinline__ void absorb_thread(State4& s, const u8* p, u32 npk) {
+    const u32 sh = misalignment(p);
+    const u32* d = (const u32*)(p - sh);
+    const u32 last = npk - 1u;
+    Dw9 ring[D];
+    u64 pk[4];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ring[k] = load_dw9(d + 8u * min((u32)k, last), sh, true);
+    u32 t0 = 0;
+    for (; t0 + 2u * D < npk; t0 += D) {
+        const u32* blk = d + 8u * (t0 + D);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            packet_words(ring[k], sh, pk);
+            update4(s, pk);
+            ring[k] = load_dw9(blk + 8 * k, sh, false);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (t0 + k < npk) {
+            packet_words(ring[k], sh, pk);
+            update4(s, pk);
+            ring[k] = load_dw9(d + 8u * min(t0 + D + k, last), sh, true);
+        }
+    }
+    t0 += D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (t0 + k < npk) {
+            packet_words(ring[k], sh, pk);
+            update4(s, pk);
+        }
+    }
+}
+
+}  // namespace hh

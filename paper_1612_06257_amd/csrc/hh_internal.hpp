@@ -1,0 +1,42 @@
+// hh_internal.hpp -- declarations shared by the host-side translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hh.h"
+
+namespace hh {
+
+struct HashArgs {
+    const uint64_t* keys;
+    uint32_t n_keys;
+    const uint32_t* key_idx;
+    const uint8_t* data;
+    uint64_t data_bytes;
+    const uint64_t* offsets;
+    const uint64_t* lengths;
+    uint64_t n;
+    uint64_t* out;
+    uint32_t width;  // output words: 1, 2 or 4
+};
+
+hh_status launch_thread(const HashArgs& a, uint64_t uniform_length, hipStream_t st);
+hh_status launch_quad(const HashArgs& a, hipStream_t st);
+hh_status launch_bucketed(const HashArgs& a, hipStream_t st);
+hh_status launch_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
+                            uint64_t* states, uint64_t n, hipStream_t st);
+hh_status launch_state_step(bool final_step, uint64_t* states, const uint32_t* state_idx,
+                            const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                            const uint64_t* lengths, const uint8_t* width_words, uint64_t* out,
+                            const uint64_t* out_offsets, uint64_t n, hipStream_t st);
+
+// current device is a gfx950 (cached per device); HH_OK or an error status
+hh_status check_device(int* device_out);
+
+// process-wide tuning (hh_set_tuning)
+hh_tuning current_tuning();
+
+void release_bucketed();
+
+}  // namespace hh

@@ -1,0 +1,267 @@
+"""Python binding of libhh.so (include/hh.h): argument marshalling only.
+
+Every entry point takes torch tensors on the current GPU, enqueues the HIP
+kernels on torch's current stream and returns without synchronising.  There
+is no fallback: if libhh.so is missing or the device is not a gfx950 the
+calls raise.
+
+Tensor conventions (uint64 quantities may be given as int64 or uint64):
+    keys      (n_keys, 4)   key k, word i = lane i
+    data      (data_bytes,) uint8, the packed messages
+    offsets   (n,)          byte offset of message j in data
+    lengths   (n,)          byte length of message j
+    key_idx   (n,) int32/uint32, or None for key 0 everywhere
+    result    (n, width) int64 -- the bits of the uint64 hash words
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhh.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_DEVICE, ERR_OUT_OF_MEMORY, ERR_LAUNCH = range(5)
+PATHS = {"auto": 0, "lane1": 1, "lane4": 2, "bucketed": 3}
+STATE_WORDS = 16
+
+
+class HHError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s (status %d)" % (what, status))
+        self.status = status
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("lane4_min_bytes", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
+                ("use_graph", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhh.so is not built (%s); run `python -m "
+                               "paper_1612_06257_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.hh_status_string.argtypes = [ctypes.c_int]
+        L.hh_status_string.restype = ctypes.c_char_p
+        L.hh_version.restype = ctypes.c_int
+        L.hh_get_constants.argtypes = [_vp, _vp]
+        L.hh_get_constants.restype = None
+        hash_args = [_vp, _u32, _vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp]
+        for name in ("hh_hash64", "hh_hash128", "hh_hash256"):
+            getattr(L, name).argtypes = hash_args
+            getattr(L, name).restype = ctypes.c_int
+        L.hh_hash_path.argtypes = [ctypes.c_int, _u32] + hash_args
+        L.hh_hash_path.restype = ctypes.c_int
+        L.hh_hash64_uniform.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp]
+        L.hh_hash64_uniform.restype = ctypes.c_int
+        L.hh_state_init.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp]
+        L.hh_state_init.restype = ctypes.c_int
+        L.hh_state_update.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp]
+        L.hh_state_update.restype = ctypes.c_int
+        L.hh_state_final.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp]
+        L.hh_state_final.restype = ctypes.c_int
+        L.hh_get_tuning.argtypes = [ctypes.POINTER(_Tuning)]
+        L.hh_get_tuning.restype = None
+        L.hh_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
+        L.hh_set_tuning.restype = ctypes.c_int
+        L.hh_release.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().hh_status_string(status).decode()
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        raise HHError(status, status_string(status))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _stream() -> _vp:
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtypes, ndim: int) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU" % name)
+    if t.dtype not in dtypes:
+        raise TypeError("%s has dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if t.dim() != ndim or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %d-d tensor" % (name, ndim))
+    return t
+
+
+_W64 = (torch.int64, torch.uint64)
+_W32 = (torch.int32, torch.uint32)
+
+
+def _msg_args(keys, data, offsets, lengths, key_idx):
+    _dev(keys, "keys", _W64, 2)
+    if keys.shape[1] != 4 or keys.shape[0] < 1:
+        raise ValueError("keys must have shape (n_keys >= 1, 4)")
+    _dev(data, "data", (torch.uint8,), 1)
+    _dev(offsets, "offsets", _W64, 1)
+    if lengths is not None:
+        _dev(lengths, "lengths", _W64, 1)
+        if lengths.numel() != offsets.numel():
+            raise ValueError("offsets and lengths differ in size")
+    if key_idx is not None:
+        _dev(key_idx, "key_idx", _W32, 1)
+        if key_idx.numel() != offsets.numel():
+            raise ValueError("key_idx and offsets differ in size")
+
+
+def hash(keys: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor, lengths: torch.Tensor,
+         key_idx: Optional[torch.Tensor] = None, width: int = 1, path: str = "auto",
+         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """HighwayHash of every message; returns (n, width) int64 hash words."""
+    if width not in (1, 2, 4):
+        raise ValueError("width must be 1, 2 or 4 words")
+    _msg_args(keys, data, offsets, lengths, key_idx)
+    n = offsets.numel()
+    if out is None:
+        out = torch.empty((n, width), dtype=torch.int64, device=offsets.device)
+    else:
+        _dev(out, "out", _W64, 2)
+        if tuple(out.shape) != (n, width):
+            raise ValueError("out must have shape (n, width)")
+    _check(lib().hh_hash_path(PATHS[path], width, _ptr(keys), keys.shape[0], _ptr(key_idx),
+                              _ptr(data), data.numel(), _ptr(offsets), _ptr(lengths), n,
+                              _ptr(out), _stream()))
+    return out
+
+
+def hash64(keys, data, offsets, lengths, key_idx=None, out=None) -> torch.Tensor:
+    return hash(keys, data, offsets, lengths, key_idx, 1, "auto", out)
+
+
+def hash128(keys, data, offsets, lengths, key_idx=None, out=None) -> torch.Tensor:
+    return hash(keys, data, offsets, lengths, key_idx, 2, "auto", out)
+
+
+def hash256(keys, data, offsets, lengths, key_idx=None, out=None) -> torch.Tensor:
+    return hash(keys, data, offsets, lengths, key_idx, 4, "auto", out)
+
+
+def hash64_uniform(keys, data, offsets, length: int, key_idx=None, out=None) -> torch.Tensor:
+    """The plain kernel: all messages have the same length (one launch)."""
+    _msg_args(keys, data, offsets, None, key_idx)
+    n = offsets.numel()
+    if out is None:
+        out = torch.empty((n, 1), dtype=torch.int64, device=offsets.device)
+    else:
+        _dev(out, "out", _W64, 2)
+        if out.shape[0] != n or out.shape[1] != 1:
+            raise ValueError("out must have shape (n, 1)")
+    _check(lib().hh_hash64_uniform(_ptr(keys), keys.shape[0], _ptr(key_idx), _ptr(data),
+                                   data.numel(), _ptr(offsets), int(length), n, _ptr(out),
+                                   _stream()))
+    return out
+
+
+def state_init(keys, n: int, key_idx=None, states=None) -> torch.Tensor:
+    """(n, 16) device states after Reset (Sec. 4.4)."""
+    _dev(keys, "keys", _W64, 2)
+    if key_idx is not None:
+        _dev(key_idx, "key_idx", _W32, 1)
+        if key_idx.numel() != n:
+            raise ValueError("key_idx must have n entries")
+    if states is None:
+        states = torch.empty((n, STATE_WORDS), dtype=torch.int64, device=keys.device)
+    else:
+        _dev(states, "states", _W64, 2)
+        if states.shape[0] < n or states.shape[1] != STATE_WORDS:
+            raise ValueError("states must have shape (>= n, 16)")
+    _check(lib().hh_state_init(_ptr(keys), keys.shape[0], _ptr(key_idx), _ptr(states), n,
+                               _stream()))
+    return states
+
+
+def state_update(states, data, offsets, lengths, state_idx=None) -> None:
+    """Fold whole packets (lengths multiples of 32) into states."""
+    _dev(states, "states", _W64, 2)
+    _dev(data, "data", (torch.uint8,), 1)
+    _dev(offsets, "offsets", _W64, 1)
+    _dev(lengths, "lengths", _W64, 1)
+    n = offsets.numel()
+    if state_idx is not None:
+        _dev(state_idx, "state_idx", _W32, 1)
+        if state_idx.numel() != n:
+            raise ValueError("state_idx must have one entry per item")
+    _check(lib().hh_state_update(_ptr(states), _ptr(state_idx), _ptr(data), data.numel(),
+                                 _ptr(offsets), _ptr(lengths), n, _stream()))
+
+
+def state_final(states, data, offsets, lengths, width_words=None, out=None, out_offsets=None,
+                state_idx=None) -> torch.Tensor:
+    """Fold the last bytes, finalize (Sec. 4.3) and write the hashes.  Without
+    out_offsets item k's words go to out[4k ..] (out has shape (n, 4))."""
+    _dev(states, "states", _W64, 2)
+    _dev(data, "data", (torch.uint8,), 1)
+    _dev(offsets, "offsets", _W64, 1)
+    _dev(lengths, "lengths", _W64, 1)
+    n = offsets.numel()
+    if width_words is not None:
+        _dev(width_words, "width_words", (torch.uint8,), 1)
+    if state_idx is not None:
+        _dev(state_idx, "state_idx", _W32, 1)
+    if out_offsets is not None:
+        _dev(out_offsets, "out_offsets", _W64, 1)
+        if out is None:
+            raise ValueError("out is required with out_offsets")
+    if out is None:
+        out = torch.zeros((n, 4), dtype=torch.int64, device=offsets.device)
+    _check(lib().hh_state_final(_ptr(states), _ptr(state_idx), _ptr(data), data.numel(),
+                                _ptr(offsets), _ptr(lengths), _ptr(width_words), _ptr(out),
+                                _ptr(out_offsets), n, _stream()))
+    return out
+
+
+def constants():
+    """The library's Sec. 4.4 constants (host copy of what the kernels use)."""
+    c0 = (ctypes.c_uint64 * 4)()
+    c1 = (ctypes.c_uint64 * 4)()
+    lib().hh_get_constants(ctypes.cast(c0, _vp), ctypes.cast(c1, _vp))
+    return [int(x) for x in c0], [int(x) for x in c1]
+
+
+def get_tuning() -> dict:
+    t = _Tuning()
+    lib().hh_get_tuning(ctypes.byref(t))
+    return {f: int(getattr(t, f)) for f, _ in _Tuning._fields_}
+
+
+def set_tuning(**kw) -> None:
+    cur = get_tuning()
+    cur.update(kw)
+    t = _Tuning(**cur)
+    _check(lib().hh_set_tuning(ctypes.byref(t)))
+
+
+def release() -> None:
+    _check(lib().hh_release())
+
+
+def to_u64(t: torch.Tensor):
+    """Hash words as a numpy uint64 array (copies to the host)."""
+    return t.detach().cpu().numpy().view("uint64")

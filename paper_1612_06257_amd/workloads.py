@@ -69,10 +69,10 @@ def _keys(rng: np.random.Generator, n_keys: int) -> np.ndarray:
 
 
 def _random_bytes(rng: np.random.Generator, n: int) -> np.ndarray:
-    """n uniform random bytes (a writable array)."""
-    if n == 0:
-        return np.zeros(0, dtype=np.uint8)
-    return np.frombuffer(bytearray(rng.bytes(n)), dtype=np.uint8)
+    """n uniform random bytes: uniform 64-bit draws viewed as little-endian
+    bytes (a writable array)."""
+    words = rng.integers(0, 2**64, size=(n + 7) // 8, dtype=np.uint64)
+    return words.astype("<u8", copy=False).view(np.uint8)[:n]
 
 
 def _packed_offsets(lengths: np.ndarray) -> np.ndarray:

@@ -1,0 +1,93 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry point
+that include/hh.h declares, rejects bad arguments before touching a device,
+and carries the Sec. 4.4 constants derived from pi."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from test_oracle_steps import _fourth_lane, _pi_fraction_words
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hh.h")
+
+
+def _hh():
+    from paper_1612_06257_amd import hh
+    return hh
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(hh_[a-z0-9_]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("hh_hash64", "hh_hash128", "hh_hash256", "hh_hash64_uniform", "hh_hash_path",
+                 "hh_state_init", "hh_state_update", "hh_state_final", "hh_status_string"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _hh().lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    hh = _hh()
+    for s in range(5):
+        assert hh.status_string(s)
+    assert hh.status_string(0) == "ok"
+    assert hh.lib().hh_version() >= 100
+
+
+def test_invalid_arguments_rejected_without_device():
+    L = _hh().lib()
+    vp = ctypes.c_void_p
+    dummy = vp(16)
+    # n > 0 with NULL keys / offsets / out
+    assert L.hh_hash64(None, 1, None, dummy, 8, dummy, dummy, 3, dummy, None) == 1
+    assert L.hh_hash64(dummy, 0, None, dummy, 8, dummy, dummy, 3, dummy, None) == 1
+    assert L.hh_hash64(dummy, 1, None, dummy, 8, None, dummy, 3, dummy, None) == 1
+    assert L.hh_hash64(dummy, 1, None, dummy, 8, dummy, dummy, 3, None, None) == 1
+    assert L.hh_hash64(dummy, 1, None, None, 8, dummy, dummy, 3, dummy, None) == 1
+    assert L.hh_hash_path(0, 3, dummy, 1, None, dummy, 8, dummy, dummy, 3, dummy, None) == 1
+    assert L.hh_hash_path(9, 1, dummy, 1, None, dummy, 8, dummy, dummy, 3, dummy, None) in (1, 2)
+    assert L.hh_state_update(None, None, dummy, 8, dummy, dummy, 2, None) == 1
+    assert L.hh_state_final(dummy, None, dummy, 8, dummy, dummy, None, None, None, 2, None) == 1
+    # n == 0 is a no-op that succeeds even with NULL pointers
+    assert L.hh_hash64(None, 0, None, None, 0, None, None, 0, None, None) == 0
+    assert L.hh_state_init(None, 0, None, None, 0, None) == 0
+
+
+def test_no_device_reported_as_unsupported():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = _hh().lib()
+    vp = ctypes.c_void_p
+    dummy = vp(16)
+    assert L.hh_hash64(dummy, 1, None, dummy, 8, dummy, dummy, 3, dummy, None) == 2
+
+
+def test_library_constants_follow_pi_derivation():
+    w = _pi_fraction_words(8)
+    c0, c1 = _hh().constants()
+    assert c0 == [_fourth_lane(w[0], w[1], w[2]), w[2], w[1], w[0]]
+    assert c1 == [_fourth_lane(w[4], w[5], w[6]), w[6], w[5], w[4]]
+
+
+def test_tuning_roundtrip():
+    hh = _hh()
+    t = hh.get_tuning()
+    hh.set_tuning(**t)
+    assert hh.get_tuning() == t
+    with pytest.raises(hh.HHError):
+        hh.set_tuning(waves_per_cu=0)
+    hh.set_tuning(**t)
