@@ -16,6 +16,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhh.so")
+PROBE_SRC = os.path.join(CSRC, "probe", "hh_probe.hip")
+PROBE_LIB = os.path.join(PKG, "libhh_probe.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -35,13 +37,21 @@ def sources() -> list:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + sources()
+def _compile(srcs: list, out: str, verbose: bool) -> str:
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Build libhh.so (the product library) and libhh_probe.so (measurement
+    kernels used by the microbenchmarks and counter calibration)."""
+    _compile(sources(), LIB, verbose)
+    _compile([PROBE_SRC], PROBE_LIB, verbose)
     return LIB
 
 

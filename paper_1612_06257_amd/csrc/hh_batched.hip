@@ -1,13 +1,341 @@
-// hh_batched.hip -- length-bucketed planner + persistent kernel (in progress:
-// routes to the quad kernel until the planner lands).
+// hh_batched.hip -- the bucketed batch path: one call hashes messages of any
+// mix of lengths.
+//
+// A message is one serial chain of ceil(L/32)+4 Updates (Sec. 4.2-4.5), so a
+// batch of uneven lengths finishes no earlier than its longest message.  The
+// path therefore (1) hashes short messages right away, one thread each, in a
+// wide grid, (2) orders the long ones by length, longest first, and (3) hashes
+// them four threads per message in a persistent grid of one wave per SIMD, so
+// that every long chain owns its SIMD's issue slots and the longest chains
+// start first (longest-processing-time-first list scheduling).
+//
+// Launch sequence on one stream (all device-side, no host synchronisation):
+//   hh_plan_reset_kernel   zero the plan counters
+//   hh_split_kernel<W>     L < threshold: hash in-thread;  else: append the
+//                          index to the long list and count it in its length
+//                          bucket (8 buckets per octave of the packet count)
+//   hh_plan_scan_kernel    bucket start offsets, longest bucket first
+//   hh_scatter_kernel      long list -> bucket order
+//   hh_long_kernel<W>      persistent: wave w first takes item w (16 messages,
+//                          4 threads each), then items from an atomic counter
+// Messages inside a bucket come out in any order; each message's result only
+// depends on its own bytes, so outputs are deterministic.
+
+#include <mutex>
+#include <vector>
 
 #include "hh_device.hpp"
 #include "hh_internal.hpp"
+#include "hh_msg.hpp"
 
 namespace hh {
 
-hh_status launch_bucketed(const HashArgs& a, hipStream_t st) { return launch_quad(a, st); }
+constexpr int kBuckets = 256;
+constexpr int kLongRing = 24;  // packets in flight per thread in hh_long_kernel
+constexpr u64 kPriorityBytes = 64u << 10;  // items this long run at wave priority 3
 
-void release_bucketed() {}
+struct Plan {
+    u32 n_long;     // messages appended to the long list
+    u32 item_next;  // next dynamic item of hh_long_kernel
+    u32 pad[2];
+    u32 hist[kBuckets];
+    u32 start[kBuckets];
+    u32 cursor[kBuckets];
+};
+
+// length bucket of a message with npk >= 1 whole packets: 8 per octave,
+// increasing with npk
+__device__ __forceinline__ u32 bucket_of(u32 npk) {
+    const u32 lz = 31u - (u32)__clz(npk);
+    const u32 sub = lz >= 3u ? (npk >> (lz - 3u)) & 7u : (npk << (3u - lz)) & 7u;
+    return lz * 8u + sub;
+}
+
+__device__ __forceinline__ u32 packets_capped(u64 len) {
+    const u64 npk = len >> 5;
+    return npk > 0xffffffffull ? 0xffffffffu : (u32)npk;
+}
+
+__global__ __launch_bounds__(256) void hh_plan_reset_kernel(Plan* __restrict__ plan) {
+    u32* w = (u32*)plan;
+    for (u32 i = threadIdx.x; i < sizeof(Plan) / 4; i += blockDim.x) w[i] = 0u;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void hh_split_kernel(
+    const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
+    const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
+    const u64* __restrict__ lengths, u64 n, u64* __restrict__ out, u64 long_min_bytes,
+    Plan* __restrict__ plan, u32* __restrict__ long_list) {
+    __shared__ u32 hist[kBuckets];
+    for (u32 i = threadIdx.x; i < kBuckets; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const u32 lane = threadIdx.x & 63u;
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    // wave-uniform loop so that every lane takes part in the ballot
+    for (u64 base = (u64)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+        const u64 j = base + lane;
+        Msg m{nullptr, 0};
+        bool is_long = false;
+        if (j < n) {
+            m = message(data, data_bytes, offsets[j], lengths[j]);
+            is_long = m.len >= long_min_bytes;
+        }
+        const u64 mask = __ballot(is_long);
+        if (mask) {
+            const u32 count = (u32)__popcll(mask);
+            const u32 leader = (u32)__ffsll((long long)mask) - 1u;
+            u32 slot0 = 0;
+            if (lane == leader) slot0 = atomicAdd(&plan->n_long, count);
+            slot0 = __builtin_amdgcn_readlane(slot0, leader);
+            if (is_long) {
+                const u32 rank = __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+                long_list[slot0 + rank] = (u32)j;
+                atomicAdd(&hist[bucket_of(packets_capped(m.len))], 1u);
+            }
+        }
+        if (j < n && !is_long) {
+            const u64* kp = keys + 4 * key_index(key_idx, n_keys, j);
+            const u64 key[4] = {kp[0], kp[1], kp[2], kp[3]};
+            u64 sum[4];
+            hash_thread(key, m.p, m.len, sum);
+#pragma unroll
+            for (int i = 0; i < W; ++i) out[(u64)W * j + i] = sum[i];
+        }
+    }
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < kBuckets; i += blockDim.x)
+        if (hist[i]) atomicAdd(&plan->hist[i], hist[i]);
+}
+
+// one block of kBuckets threads: exclusive prefix over buckets, longest first
+__global__ __launch_bounds__(kBuckets) void hh_plan_scan_kernel(Plan* __restrict__ plan,
+                                                                u32 first_dynamic_item) {
+    __shared__ u32 s[kBuckets];
+    const u32 t = threadIdx.x;
+    const u32 b = kBuckets - 1u - t;  // t = 0 is the longest bucket
+    const u32 c = plan->hist[b];
+    s[t] = c;
+    __syncthreads();
+    for (u32 d = 1; d < kBuckets; d <<= 1) {
+        const u32 v = t >= d ? s[t - d] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    plan->start[b] = s[t] - c;
+    plan->cursor[b] = 0u;
+    if (t == 0) plan->item_next = first_dynamic_item;
+}
+
+__global__ __launch_bounds__(256) void hh_scatter_kernel(
+    const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
+    const u64* __restrict__ lengths, Plan* __restrict__ plan, const u32* __restrict__ long_list,
+    u32* __restrict__ order) {
+    const u32 n_long = plan->n_long;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n_long; i += gridDim.x * blockDim.x) {
+        const u32 j = long_list[i];
+        const Msg m = message(data, data_bytes, offsets[j], lengths[j]);
+        const u32 b = bucket_of(packets_capped(m.len));
+        const u32 pos = atomicAdd(&plan->cursor[b], 1u);
+        order[plan->start[b] + pos] = j;
+    }
+}
+
+// Persistent: 16 messages per item, 4 threads per message.  Wave w (numbered
+// so that waves 0..gridDim.x-1 are the first waves of distinct workgroups)
+// takes item w first, then items from plan->item_next.
+template <int W>
+__global__ __launch_bounds__(256) void hh_long_kernel(
+    const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
+    const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
+    const u64* __restrict__ lengths, u64* __restrict__ out, Plan* __restrict__ plan,
+    const u32* __restrict__ order) {
+    extern __shared__ u32 lds_reserve[];  // sized by the launch to set residency
+    const u32 lane = threadIdx.x & 63u;
+    const int q = (int)(lane & 3u);
+    const u32 n_long = plan->n_long;
+    const u32 n_items = (n_long + 15u) >> 4;
+    u32 item = (threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+    if (item >= n_items && lane == 0 && threadIdx.x == 0) lds_reserve[0] = 0u;
+    while (item < n_items) {
+        const u32 k = 16u * item + (lane >> 2);
+        // items come longest first: the item's first message decides whether
+        // this wave's chain is long enough to claim its SIMD's issue slots
+        const u32 first = __builtin_amdgcn_readfirstlane(order[16u * item]);
+        if (lengths[first] >= kPriorityBytes)
+            __builtin_amdgcn_s_setprio(3);
+        else
+            __builtin_amdgcn_s_setprio(0);
+        if (k < n_long) {
+            const u32 j = order[k];
+            const u64 key_q = keys[4 * key_index(key_idx, n_keys, j) + q];
+            const Msg m = message(data, data_bytes, offsets[j], lengths[j]);
+            const u64 sum = hash_quad<kLongRing>(key_q, m.p, m.len, q);
+            if (q < W) out[(u64)W * j + q] = sum;
+        }
+        u32 nxt = 0;
+        if (lane == 0) nxt = atomicAdd(&plan->item_next, 1u);
+        item = __builtin_amdgcn_readfirstlane(nxt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side: per (device, stream) workspace
+
+namespace {
+
+struct Workspace {
+    int device;
+    hipStream_t stream;
+    u8* mem;
+    u64 cap_msgs;
+    Plan* plan;
+    u32* long_list;
+    u32* order;
+};
+
+std::mutex g_ws_mutex;
+std::vector<Workspace> g_ws;
+
+struct DeviceInfo {
+    int cus;
+    int lds_per_cu;
+    int lds_per_block;
+};
+
+DeviceInfo device_info(int dev) {
+    static DeviceInfo cache[64];
+    static bool have[64];
+    if (dev >= 0 && dev < 64 && have[dev]) return cache[dev];
+    DeviceInfo d{0, 0, 0};
+    if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        d.cus <= 0)
+        d.cus = 256;
+    if (hipDeviceGetAttribute(&d.lds_per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              dev) != hipSuccess)
+        d.lds_per_cu = 0;
+    if (hipDeviceGetAttribute(&d.lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+        hipSuccess)
+        d.lds_per_block = 0;
+    (void)hipGetLastError();
+    if (dev >= 0 && dev < 64) {
+        cache[dev] = d;
+        have[dev] = true;
+    }
+    return d;
+}
+
+u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
+
+hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out) {
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    Workspace* ws = nullptr;
+    for (auto& w : g_ws)
+        if (w.device == dev && w.stream == st) ws = &w;
+    if (!ws) {
+        g_ws.push_back(Workspace{dev, st, nullptr, 0, nullptr, nullptr, nullptr});
+        ws = &g_ws.back();
+    }
+    if (ws->cap_msgs < n || !ws->mem) {
+        u64 cap = ws->cap_msgs ? ws->cap_msgs : 1024;
+        while (cap < n) cap *= 2;
+        const u64 plan_bytes = align_up(sizeof(Plan), 256);
+        const u64 list_bytes = align_up(4 * cap, 256);
+        u8* mem = nullptr;
+        if (ws->mem) {
+            // earlier work on this stream may still read the old buffers
+            if (hipStreamSynchronize(st) != hipSuccess) return HH_ERR_LAUNCH;
+            (void)hipFree(ws->mem);
+            ws->mem = nullptr;
+            ws->cap_msgs = 0;
+        }
+        if (hipMalloc(&mem, plan_bytes + 2 * list_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return HH_ERR_OUT_OF_MEMORY;
+        }
+        ws->mem = mem;
+        ws->cap_msgs = cap;
+        ws->plan = (Plan*)mem;
+        ws->long_list = (u32*)(mem + plan_bytes);
+        ws->order = (u32*)(mem + plan_bytes + list_bytes);
+    }
+    *out = ws;
+    return HH_OK;
+}
+
+template <int W>
+hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, const DeviceInfo& di,
+                            const hh_tuning& tun) {
+    const u32 waves_per_cu = tun.waves_per_cu ? tun.waves_per_cu : 4u;
+    const u32 blocks_per_cu = (waves_per_cu + 3u) / 4u;
+    const u32 long_blocks = (u32)di.cus * blocks_per_cu;
+    // LDS per workgroup so that only blocks_per_cu workgroups fit on a CU
+    u32 lds = 0;
+    if (di.lds_per_cu > 0) {
+        lds = (u32)di.lds_per_cu / (blocks_per_cu + 1u) + 1024u;
+        if (di.lds_per_block > 0 && lds > (u32)di.lds_per_block) lds = (u32)di.lds_per_block;
+        lds &= ~255u;
+    }
+    const unsigned split_blocks = (unsigned)std::min<u64>((a.n + 255) / 256, 8192);
+    hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan);
+    hipLaunchKernelGGL(hh_split_kernel<W>, dim3(split_blocks), dim3(256), 0, st, a.keys, a.n_keys,
+                       a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.n, a.out,
+                       (u64)tun.lane4_min_bytes, ws->plan, ws->long_list);
+    hipLaunchKernelGGL(hh_plan_scan_kernel, dim3(1), dim3(kBuckets), 0, st, ws->plan,
+                       long_blocks * 4u);
+    const unsigned scatter_blocks = (unsigned)std::min<u64>((a.n + 255) / 256, 1024);
+    hipLaunchKernelGGL(hh_scatter_kernel, dim3(scatter_blocks), dim3(256), 0, st, a.data,
+                       a.data_bytes, a.offsets, a.lengths, ws->plan, ws->long_list, ws->order);
+    hipLaunchKernelGGL(hh_long_kernel<W>, dim3(long_blocks), dim3(256), lds, st, a.keys, a.n_keys,
+                       a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.out, ws->plan,
+                       ws->order);
+    return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+}
+
+}  // namespace
+
+// Messages are processed in chunks of at most 2^30 so that indices fit 32 bits.
+hh_status launch_bucketed(const HashArgs& a, hipStream_t st) {
+    int dev = 0;
+    hh_status s = check_device(&dev);
+    if (s != HH_OK) return s;
+    const DeviceInfo di = device_info(dev);
+    const hh_tuning tun = current_tuning();
+    const u64 chunk = 1ull << 30;
+    for (u64 first = 0; first < a.n; first += chunk) {
+        HashArgs c = a;
+        c.n = std::min<u64>(chunk, a.n - first);
+        c.offsets = a.offsets + first;
+        c.lengths = a.lengths + first;
+        c.key_idx = a.key_idx ? a.key_idx + first : nullptr;
+        c.out = a.out + first * a.width;
+        Workspace* ws = nullptr;
+        if ((s = get_workspace(dev, st, c.n, &ws)) != HH_OK) return s;
+        switch (a.width) {
+            case 1: s = launch_bucketed_w<1>(c, st, ws, di, tun); break;
+            case 2: s = launch_bucketed_w<2>(c, st, ws, di, tun); break;
+            default: s = launch_bucketed_w<4>(c, st, ws, di, tun); break;
+        }
+        if (s != HH_OK) return s;
+    }
+    return HH_OK;
+}
+
+void release_bucketed() {
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    for (auto& w : g_ws) {
+        if (w.mem) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(w.device);
+            (void)hipStreamSynchronize(w.stream);
+            (void)hipFree(w.mem);
+            (void)hipSetDevice(cur);
+        }
+    }
+    g_ws.clear();
+}
 
 }  // namespace hh

@@ -11,92 +11,9 @@
 
 #include "hh_device.hpp"
 #include "hh_internal.hpp"
+#include "hh_msg.hpp"
 
 namespace hh {
-
-// ---------------------------------------------------------------------------
-// per-message setup shared by the kernels
-
-struct Msg {
-    const u8* p;
-    u64 len;
-};
-
-__device__ __forceinline__ Msg message(const u8* data, u64 data_bytes, u64 off, u64 len) {
-    off = off < data_bytes ? off : data_bytes;
-    const u64 room = data_bytes - off;
-    return Msg{data + off, len < room ? len : room};
-}
-
-__device__ __forceinline__ u64 key_index(const u32* key_idx, u32 n_keys, u64 j) {
-    if (!key_idx) return 0;
-    const u32 k = key_idx[j];
-    return k < n_keys ? k : n_keys - 1u;
-}
-
-// Sec. 4.5 remainder step on a whole state held by one thread.
-__device__ __forceinline__ void remainder4(State4& s, const u8* tail, u32 r) {
-    const u64 inject = ((u64)r << 32) + r;
-    u64 pk[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        s.v0[i] += inject;
-        s.v1[i] = rotl_halves(s.v1[i], r);
-        pk[i] = make64(remainder_dword(tail, r, 2 * i), remainder_dword(tail, r, 2 * i + 1));
-    }
-    update4(s, pk);
-}
-
-// Sec. 4.5 remainder step, quad layout (thread holds lane q).
-__device__ __forceinline__ void remainder1(State1& s, const u8* tail, u32 r, int q) {
-    s.v0 += ((u64)r << 32) + r;
-    s.v1 = rotl_halves(s.v1, r);
-    update1(s, make64(remainder_dword(tail, r, 2 * q), remainder_dword(tail, r, 2 * q + 1)));
-}
-
-// Packets per absorb call: lengths below 2^36 bytes need a single call.
-constexpr u64 kMaxPacketsPerCall = 1ull << 31;
-
-constexpr int kThreadRing = 2;  // packets in flight per thread (thread layout)
-constexpr int kQuadRing = 8;    // packets in flight per thread (quad layout)
-
-// The whole hash of one message in one thread; returns the final lane sums.
-__device__ __forceinline__ void hash_thread(const u64* key, const u8* p, u64 len, u64 sum[4]) {
-    State4 s;
-    reset4(s, key);
-    u64 nfull = len >> 5;
-    const u8* cur = p;
-    while (nfull) {
-        const u32 npk = (u32)(nfull < kMaxPacketsPerCall ? nfull : kMaxPacketsPerCall);
-        absorb_thread<kThreadRing>(s, cur, npk);
-        cur += 32 * (u64)npk;
-        nfull -= npk;
-    }
-    const u32 r = (u32)(len & 31u);
-    if (r) remainder4(s, cur, r);
-    finalize4(s, sum);
-}
-
-// Whole packets of a message on a quad (thread q absorbs lane q).
-__device__ __forceinline__ const u8* absorb_quad_all(State1& s, const u8* p, u64 nfull, int q) {
-    while (nfull) {
-        const u32 npk = (u32)(nfull < kMaxPacketsPerCall ? nfull : kMaxPacketsPerCall);
-        absorb_quad<kQuadRing>(s, p + 8 * q, npk);
-        p += 32 * (u64)npk;
-        nfull -= npk;
-    }
-    return p;
-}
-
-// The whole hash of one message on a quad; returns lane q of the sums.
-__device__ __forceinline__ u64 hash_quad(u64 key_q, const u8* p, u64 len, int q) {
-    State1 s;
-    reset1(s, key_q, q);
-    const u8* tail = absorb_quad_all(s, p, len >> 5, q);
-    const u32 r = (u32)(len & 31u);
-    if (r) remainder1(s, tail, r, q);
-    return finalize1(s);
-}
 
 template <int W>
 __global__ __launch_bounds__(256) void hh_thread_kernel(
@@ -125,7 +42,7 @@ __global__ __launch_bounds__(256) void hh_quad_kernel(
     for (u64 j = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 2; j < n; j += stride) {
         const u64 key_q = keys[4 * key_index(key_idx, n_keys, j) + q];
         const Msg m = message(data, data_bytes, offsets[j], lengths[j]);
-        const u64 sum = hash_quad(key_q, m.p, m.len, q);
+        const u64 sum = hash_quad<kQuadRing>(key_q, m.p, m.len, q);
         if (q < W) out[(u64)W * j + q] = sum;
     }
 }
@@ -174,7 +91,7 @@ __global__ __launch_bounds__(256) void hh_state_step_kernel(
         const Msg m = message(data, data_bytes, offsets[k], lengths[k]);
         State1 s;
         load_state1(s, st, q);
-        const u8* tail = absorb_quad_all(s, m.p, m.len >> 5, q);
+        const u8* tail = absorb_quad_all<kQuadRing>(s, m.p, m.len >> 5, q);
         if (!FINAL) {
             store_state1(s, st, q);
         } else {
