@@ -1,0 +1,273 @@
+"""Benchmark: batched HighwayHash-64 on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lognormal]
+
+One step = one hh_hash64 call over the whole batch (planner + every hash: key
+setup, packets, remainder, finalization, output), inputs already resident in
+HBM.  The default workload is the uneven-length batch: 2^16 messages with
+log-normal lengths (median 4 KiB, sigma 2.15, clipped to [1 B, 1 MiB]),
+about 2.17 GB packed into one buffer, one key.
+
+Printed as one JSON line:
+  value        GB/s hashed, batched path (total message bytes / time per step)
+  plain        the same batch through the plain one-thread-per-message kernel,
+               one launch per distinct length (the baseline the batched path
+               is measured against), plus single-launch variants
+  roofline     the dominant kernel (the persistent long-message kernel):
+               algorithmic bytes per launch / its mean duration, timed with
+               HIP events around each launch on the launch stream
+  critical_path  the longest message's serial Update chain at the measured
+               single-wave Update time
+  cpu_baseline the CPU oracle on the host's cores, same batch
+  serving      p50/p99 latency of the serving loop (if run)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GB/s hashed (HighwayHash-64) batched vs plain on 1 MI355X; p99 request latency"
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
+OUT_BYTES = 8                   # HighwayHash-64 result per message
+KEY_BYTES = 32
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILE_DIR, "hh_long_kernel_lognormal_traffic.json")
+CHAIN_FILE = os.path.join(PROFILE_DIR, "microbench_update_chain.json")
+KERNEL_SOURCES = ["paper_1612_06257_amd/csrc/hh_batched.hip", "paper_1612_06257_amd/csrc/hh_msg.hpp",
+                  "paper_1612_06257_amd/csrc/hh_device.hpp"]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(name: str):
+    from paper_1612_06257_amd import workloads as W
+    if name == "lognormal":
+        return W.lognormal()
+    if name == "plain_fixed":
+        return W.plain_fixed()
+    if name == "short_mixed":
+        return W.short_mixed()
+    if name == "prf_counters":
+        return W.prf_counters()
+    raise SystemExit("unknown workload " + name)
+
+
+def to_device(b):
+    import torch
+    k = torch.from_numpy(b.keys).view(torch.int64).cuda()
+    d = torch.from_numpy(b.data).cuda()
+    o = torch.from_numpy(b.offsets).view(torch.int64).cuda()
+    L = torch.from_numpy(b.lengths).view(torch.int64).cuda()
+    ki = None if b.key_idx is None else torch.from_numpy(b.key_idx).view(torch.int32).cuda()
+    return k, ki, d, o, L
+
+
+def time_plain(hh, b, dev):
+    """The plain kernel, one launch per distinct length, on one stream."""
+    import numpy as np
+    import torch
+    k, ki, d, o, L = dev
+    order = np.argsort(b.lengths, kind="stable")
+    lens_sorted = b.lengths[order]
+    uniq, starts = np.unique(lens_sorted, return_index=True)
+    ends = np.append(starts[1:], lens_sorted.size)
+    order_t = torch.from_numpy(order.astype(np.int64)).cuda()
+    off_sorted = o[order_t].contiguous()
+    ki_sorted = None if ki is None else ki[order_t].contiguous()
+    out = torch.empty((b.n, 1), dtype=torch.int64, device="cuda")
+    lib = hh.lib()
+    stream = hh._stream()
+    keys_p = hh._ptr(k)
+    groups = []
+    for Lg, s, e in zip(uniq.tolist(), starts.tolist(), ends.tolist()):
+        groups.append((int(Lg), off_sorted[s:e], None if ki_sorted is None else ki_sorted[s:e],
+                       out[s:e]))
+
+    def run():
+        for Lg, og, kg, outg in groups:
+            st = lib.hh_hash64_uniform(keys_p, k.shape[0], hh._ptr(kg), hh._ptr(d), d.numel(),
+                                       hh._ptr(og), Lg, og.numel(), hh._ptr(outg), stream)
+            if st != 0:
+                raise hh.HHError(st, hh.status_string(st))
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    got = np.empty(b.n, dtype=np.uint64)
+    got[order] = hh.to_u64(out)[:, 0]
+    return {"value": b.total_bytes / sec / 1e9, "unit": "GB/s", "ms": sec * 1e3,
+            "launches": len(groups), "kernel": "hh_thread_kernel (one thread per message)"}, got
+
+
+def time_single_launch(hh, b, dev, path):
+    import torch
+    k, ki, d, o, L = dev
+    out = torch.empty((b.n, 1), dtype=torch.int64, device="cuda")
+    hh.hash(k, d, o, L, ki, 1, path, out)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        hh.hash(k, d, o, L, ki, 1, path, out)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    return {"value": b.total_bytes / sec / 1e9, "unit": "GB/s", "ms": sec * 1e3}
+
+
+def cpu_baseline(b):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    ref = oracle.batch(b.keys, b.key_idx, b.data, b.offsets, b.lengths, 1, n_threads=threads)
+    sec = time.perf_counter() - t0
+    return {"value": b.total_bytes / sec / 1e9, "unit": "GB/s", "cores": threads,
+            "kind": "oracle", "sample": "the whole batch once (%d messages, %d bytes)"
+            % (b.n, b.total_bytes), "seconds": sec}, ref[:, 0]
+
+
+def load_json(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="lognormal",
+                    choices=["lognormal", "plain_fixed", "short_mixed", "prf_counters"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serving", action="store_true", help="also run the serving loop")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the batch path has no multi-GPU mode "
+              "(messages are independent; see the design notes for how it would shard)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1612_06257_amd import hh
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    hh.lib()
+    t_gen = time.perf_counter()
+    b = make_workload(args.workload)
+    gen_s = time.perf_counter() - t_gen
+    dev = to_device(b)
+    k, ki, d, o, L = dev
+    out = torch.empty((b.n, 1), dtype=torch.int64, device="cuda")
+
+    print("[bench] workload %s: %d messages, %d bytes (generated in %.1f s)"
+          % (b.name, b.n, b.total_bytes, gen_s), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        hh.hash(k, d, o, L, ki, 1, "auto", out)
+    torch.cuda.synchronize()
+    hh.timing_enable(True)
+    hh.timing_collect()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hh.hash(k, d, o, L, ki, 1, "auto", out)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    launches, long_ms = hh.timing_collect()
+    hh.timing_enable(False)
+    ms_per_step = sec * 1e3 / args.steps
+    value = b.total_bytes * args.steps / sec / 1e9
+    gpu_hash = hh.to_u64(out)[:, 0].copy()
+    print("[bench] batched: %.3f ms/step, %.1f GB/s" % (ms_per_step, value), file=sys.stderr,
+          flush=True)
+
+    # roofline of the dominant kernel (persistent long-message kernel)
+    lengths = b.lengths.astype(np.int64)
+    thr = hh.get_tuning()["lane4_min_bytes"]
+    long_mask = lengths >= thr
+    long_bytes = int(lengths[long_mask].sum()) + OUT_BYTES * int(long_mask.sum()) + KEY_BYTES
+    long_ms_mean = long_ms / launches if launches else None
+    achieved = long_bytes / (long_ms_mean * 1e6) if long_ms_mean else None
+    traffic = None
+    tr = load_json(TRAFFIC_FILE)
+    if tr and tr.get("source_sha") == kernel_source_sha() and tr.get("workload") == b.name:
+        traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "hh_long_kernel", "achieved": achieved,
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": traffic,
+                "algorithmic_bytes_per_launch": long_bytes,
+                "kernel_ms_mean": long_ms_mean, "launches_timed": launches}
+
+    # critical path: longest message x measured single-wave Update time
+    chain = load_json(CHAIN_FILE) or {}
+    t_upd_ns = chain.get("quad_ns_per_update")
+    longest = int(lengths.max()) if lengths.size else 0
+    n_upd = (longest + 31) // 32 + 4
+    critical = None
+    if t_upd_ns:
+        floor_ms = n_upd * t_upd_ns * 1e-6
+        critical = {"longest_message_bytes": longest, "updates": n_upd,
+                    "ns_per_update": t_upd_ns, "floor_ms": floor_ms,
+                    "frac_of_step": floor_ms / ms_per_step}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": b.name, "n_msgs": b.n, "bytes": b.total_bytes, "seed": b.seed,
+                   "output_bits": 64, "path": "bucketed (planner + persistent kernel)"},
+        "messages_per_s": b.n * args.steps / sec,
+        "roofline": roofline,
+        "critical_path": critical,
+    }
+
+    if not args.no_plain:
+        plain, plain_hash = time_plain(hh, b, dev)
+        plain["bit_exact_with_batched"] = bool(np.array_equal(plain_hash, gpu_hash))
+        result["plain"] = plain
+        result["batched_over_plain"] = value / plain["value"]
+        result["single_launch"] = {p: time_single_launch(hh, b, dev, p) for p in ("lane1", "lane4")}
+        print("[bench] plain: %d launches, %.1f ms" % (plain["launches"], plain["ms"]),
+              file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        cb, ref = cpu_baseline(b)
+        result["cpu_baseline"] = cb
+        result["parity"] = "bit-exact" if np.array_equal(ref, gpu_hash) else "MISMATCH"
+    else:
+        result["cpu_baseline"] = None
+
+    result["serving"] = None
+    if args.serving:
+        from paper_1612_06257_amd import serve
+        result["serving"] = serve.bench_summary()
+
+    print(json.dumps(result))
+    return 0 if result.get("parity", "bit-exact") == "bit-exact" else 3
+
+
+if __name__ == "__main__":
+    sys.exit(main())

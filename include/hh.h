@@ -117,19 +117,21 @@ hh_status hh_hash64_uniform(const uint64_t* keys, uint32_t n_keys, const uint32_
 hh_status hh_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
                         uint64_t* states, uint64_t n, void* stream);
 
-/* Item k folds data[offsets[k] .. + lengths[k]) into state state_idx[k]
- * (state_idx NULL: state k).  Every lengths[k] must be a multiple of 32
- * (HH_ERR_INVALID_ARG is not checked on the device: a length that is not is
- * rounded down).  Two items must not name the same state in one call. */
+/* Item k folds the whole packets of data[offsets[k] .. + lengths[k]) into
+ * state state_idx[k] (state_idx NULL: state k) and stores the state back.
+ * lengths[k] should be a multiple of 32; only its whole packets are consumed
+ * (lengths[k] rounded down to a multiple of 32).  Two items must not name the
+ * same state in one call. */
 hh_status hh_state_update(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
                           uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
                           uint64_t n, void* stream);
 
-/* Item k folds its bytes (any length: whole packets, then the remainder
- * step with r = lengths[k] mod 32, which must equal the stream's total size
- * mod 32) into state state_idx[k], finalizes and writes width_words[k]
- * (1, 2 or 4; NULL = 1) words to out[out_offsets[k] ..] (out_offsets NULL:
- * out[4*k ..]).  The state is left finalized (not reusable). */
+/* Item k takes state state_idx[k], folds in its bytes (any length: whole
+ * packets, then the remainder step with r = lengths[k] mod 32, which is the
+ * stream's total size mod 32 because earlier updates were whole packets),
+ * finalizes and writes width_words[k] (1, 2 or 4; NULL = 1) words to
+ * out[out_offsets[k] ..] (out_offsets NULL: out[4*k ..]).  The stored state
+ * is not modified, so a stream can be finished more than once. */
 hh_status hh_state_final(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
                          uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
                          const uint8_t* width_words, uint64_t* out, const uint64_t* out_offsets,
@@ -149,6 +151,17 @@ hh_status hh_set_tuning(const hh_tuning* t);
 
 /* Free the library's per-device workspaces and cached graphs. */
 hh_status hh_release(void);
+
+/* ---------------------------------------------------------------------------
+ * Measurement hook (benchmarks, profilers).  While enabled, every call of the
+ * bucketed path records a pair of HIP events on its stream around its
+ * persistent long-message kernel, the path's dominant kernel.
+ * hh_timing_collect waits for every recorded pair, returns how many launches
+ * were recorded and their summed duration in milliseconds, and forgets them.
+ * Recording stops at 4096 pending pairs.  Process-wide; not for concurrent
+ * use from several threads. */
+hh_status hh_timing_enable(int enable);
+hh_status hh_timing_collect(uint32_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

@@ -182,4 +182,10 @@ hh_status hh_release(void) {
     return HH_OK;
 }
 
+hh_status hh_timing_enable(int enable) { return hh::timing_enable(enable != 0); }
+
+hh_status hh_timing_collect(uint32_t* launches, double* total_ms) {
+    return hh::timing_collect(launches, total_ms);
+}
+
 }  // extern "C"

@@ -199,6 +199,40 @@ struct Workspace {
 std::mutex g_ws_mutex;
 std::vector<Workspace> g_ws;
 
+// measurement hook: event pairs around hh_long_kernel launches
+struct EventPair {
+    hipEvent_t start, stop;
+};
+std::mutex g_timing_mutex;
+bool g_timing_on = false;
+std::vector<EventPair> g_timing_pool;     // created, reusable
+std::vector<EventPair> g_timing_pending;  // recorded, not yet collected
+constexpr size_t kMaxPendingPairs = 4096;
+
+EventPair* timing_begin(hipStream_t st) {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    if (!g_timing_on || g_timing_pending.size() >= kMaxPendingPairs) return nullptr;
+    EventPair p;
+    if (!g_timing_pool.empty()) {
+        p = g_timing_pool.back();
+        g_timing_pool.pop_back();
+    } else if (hipEventCreate(&p.start) != hipSuccess || hipEventCreate(&p.stop) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipEventRecord(p.start, st) != hipSuccess) {
+        (void)hipGetLastError();
+        g_timing_pool.push_back(p);
+        return nullptr;
+    }
+    g_timing_pending.push_back(p);
+    return &g_timing_pending.back();
+}
+
+void timing_end(EventPair* p, hipStream_t st) {
+    if (p && hipEventRecord(p->stop, st) != hipSuccess) (void)hipGetLastError();
+}
+
 struct DeviceInfo {
     int cus;
     int lds_per_cu;
@@ -288,10 +322,13 @@ hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, co
     const unsigned scatter_blocks = (unsigned)std::min<u64>((a.n + 255) / 256, 1024);
     hipLaunchKernelGGL(hh_scatter_kernel, dim3(scatter_blocks), dim3(256), 0, st, a.data,
                        a.data_bytes, a.offsets, a.lengths, ws->plan, ws->long_list, ws->order);
+    EventPair* ev = timing_begin(st);
     hipLaunchKernelGGL(hh_long_kernel<W>, dim3(long_blocks), dim3(256), lds, st, a.keys, a.n_keys,
                        a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.out, ws->plan,
                        ws->order);
-    return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+    const bool ok = hipGetLastError() == hipSuccess;
+    timing_end(ev, st);
+    return ok ? HH_OK : HH_ERR_LAUNCH;
 }
 
 }  // namespace
@@ -321,6 +358,35 @@ hh_status launch_bucketed(const HashArgs& a, hipStream_t st) {
         if (s != HH_OK) return s;
     }
     return HH_OK;
+}
+
+hh_status timing_enable(bool on) {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    g_timing_on = on;
+    return HH_OK;
+}
+
+hh_status timing_collect(uint32_t* launches, double* total_ms) {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    double sum = 0.0;
+    uint32_t n = 0;
+    hh_status s = HH_OK;
+    for (auto& p : g_timing_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.stop) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+            sum += ms;
+            ++n;
+        } else {
+            (void)hipGetLastError();
+            s = HH_ERR_LAUNCH;
+        }
+        g_timing_pool.push_back(p);
+    }
+    g_timing_pending.clear();
+    if (launches) *launches = n;
+    if (total_ms) *total_ms = sum;
+    return s;
 }
 
 void release_bucketed() {

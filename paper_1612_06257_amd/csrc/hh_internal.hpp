@@ -38,5 +38,7 @@ hh_status check_device(int* device_out);
 hh_tuning current_tuning();
 
 void release_bucketed();
+hh_status timing_enable(bool on);
+hh_status timing_collect(uint32_t* launches, double* total_ms);
 
 }  // namespace hh

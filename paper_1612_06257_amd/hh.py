@@ -78,6 +78,11 @@ def lib() -> ctypes.CDLL:
         L.hh_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         L.hh_set_tuning.restype = ctypes.c_int
         L.hh_release.restype = ctypes.c_int
+        L.hh_timing_enable.argtypes = [ctypes.c_int]
+        L.hh_timing_enable.restype = ctypes.c_int
+        L.hh_timing_collect.argtypes = [ctypes.POINTER(ctypes.c_uint32),
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.hh_timing_collect.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -260,6 +265,19 @@ def set_tuning(**kw) -> None:
 
 def release() -> None:
     _check(lib().hh_release())
+
+
+def timing_enable(on: bool = True) -> None:
+    """Record HIP events around each bucketed call's long-message kernel."""
+    _check(lib().hh_timing_enable(int(bool(on))))
+
+
+def timing_collect():
+    """(launches, total_ms) of the long-message kernels recorded so far."""
+    n = ctypes.c_uint32()
+    ms = ctypes.c_double()
+    _check(lib().hh_timing_collect(ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
 
 
 def to_u64(t: torch.Tensor):

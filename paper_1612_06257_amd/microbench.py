@@ -128,6 +128,7 @@ def copy(L, nbytes: int, n_blocks: int = 8192, reps: int = 1):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--json", default=None)
+    ap.add_argument("--summary", default=None, help="write the key figures as JSON here")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run the copy kernel on this many bytes (for counters)")
     args = ap.parse_args(argv)
@@ -156,6 +157,30 @@ def main(argv=None):
         with open(args.json, "w") as f:
             for r in recs:
                 f.write(json.dumps(r) + "\n")
+    if args.summary:
+        with open(args.summary, "w") as f:
+            json.dump(summarize(recs, "python -m paper_1612_06257_amd.microbench " +
+                                " ".join(argv if argv is not None else sys.argv[1:])), f,
+                      indent=1)
+            f.write("\n")
+
+
+def summarize(recs, command: str) -> dict:
+    """Key figures: single-wave Update time per layout, op rates, HBM read."""
+    out = {"command": command}
+    for r in recs:
+        if r["kind"] == "chain" and r["n_waves"] == 1:
+            lay = r["layout"]
+            out[lay + "_cycles_per_update"] = r["cycles_per_update_median"]
+            out[lay + "_ns_per_update"] = r["ns_per_update_wall"]
+        if r["kind"] == "chain" and r["prio_waves"]:
+            out[r["layout"] + "_prio_cycles_per_update_with_%d_waves" % r["n_waves"]] = \
+                r["cycles_per_update_prio_max"]
+        if r["kind"] == "op_rate":
+            out["op_rate_" + r["op"]] = r["lane_ops_per_s"]
+        if r["kind"] == "read":
+            out["hbm_read_GBps"] = r["GBps"]
+    return out
 
 
 if __name__ == "__main__":

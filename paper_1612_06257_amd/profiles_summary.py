@@ -1,0 +1,70 @@
+"""Turn rocprofv3 CSV output into the short summaries kept under profiles/.
+
+    python -m paper_1612_06257_amd.profiles_summary stats  <kernel_stats.csv> <out.md> <command>
+    python -m paper_1612_06257_amd.profiles_summary traffic <fetch.csv> <write.csv> \
+        <copy_fetch.csv> <copy_write.csv> <copy_bytes> <workload> <out.json>
+
+`traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of
+hh_long_kernel by the factor that makes the same counters read the known size
+of a plain copy kernel, and records the hash of the kernel sources so that a
+later benchmark only reuses the figure while the kernel is unchanged.
+"""
+import csv
+import json
+import sys
+
+
+def kernel_stats(path, out, command):
+    rows = list(csv.DictReader(open(path)))
+    lines = ["# rocprofv3 --kernel-trace --stats", "", "Command: `%s`" % command, "",
+             "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append("| %s | %s | %.1f | %.1f | %.1f | %.2f |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def _per_kernel(path):
+    agg = {}
+    for r in csv.DictReader(open(path)):
+        agg.setdefault(r["Kernel_Name"].split("(")[0].replace("void ", ""), []).append(
+            float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out, kernel="hh::hh_long_kernel<1>"):
+    sys.path.insert(0, ".")
+    import bench
+    f = _per_kernel(fetch)
+    w = _per_kernel(write)
+    cf = _per_kernel(copy_fetch)["hh::hh_probe_copy_kernel"]
+    cw = _per_kernel(copy_write)["hh::hh_probe_copy_kernel"]
+    f_factor = copy_bytes / (cf * 1024.0)
+    w_factor = copy_bytes / (cw * 1024.0)
+    rec = {
+        "kernel": kernel, "workload": workload, "source_sha": bench.kernel_source_sha(),
+        "fetch_kib_per_dispatch": f[kernel], "write_kib_per_dispatch": w[kernel],
+        "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+        "fetch_scale": f_factor, "write_scale": w_factor,
+        "hbm_bytes_per_launch": f[kernel] * 1024.0 * f_factor + w[kernel] * 1024.0 * w_factor,
+        "other_kernels_fetch_kib": {k: v for k, v in f.items() if k != kernel},
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain",
+            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain",
+            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
+            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
+        ],
+    }
+    json.dump(rec, open(out, "w"), indent=1)
+    open(out, "a").write("\n")
+    return rec
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        kernel_stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    else:
+        print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5],
+                                 int(sys.argv[6]), sys.argv[7], sys.argv[8]), indent=1))
