@@ -163,9 +163,8 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the batch path has no multi-GPU mode "
-              "(messages are independent; see the design notes for how it would shard)",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: messages are independent and would shard "
+              "across GPUs by bytes, but this build has no multi-GPU path", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -223,7 +222,8 @@ def main(argv=None) -> int:
 
     # critical path: longest message x measured single-wave Update time
     chain = load_json(CHAIN_FILE) or {}
-    t_upd_ns = chain.get("quad_ns_per_update")
+    ring = hh.get_tuning()["long_ring"]
+    t_upd_ns = chain.get("quad_loop_ring%d_ns_per_update" % ring) or chain.get("quad_ns_per_update")
     longest = int(lengths.max()) if lengths.size else 0
     n_upd = (longest + 31) // 32 + 4
     critical = None

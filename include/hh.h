@@ -140,10 +140,13 @@ hh_status hh_state_final(uint64_t* states, const uint32_t* state_idx, const uint
 /* ---------------------------------------------------------------------------
  * Tuning of the bucketed path (host-side settings, process-wide). */
 typedef struct {
-    uint32_t lane4_min_bytes;   /* messages at least this long use 4 threads each */
-    uint32_t waves_per_cu;      /* persistent grid: CUs x waves_per_cu waves */
+    uint32_t lane4_min_bytes;   /* messages at least this long go to the persistent
+                                   kernel (four threads each); shorter ones are
+                                   hashed one thread each while the plan is built */
+    uint32_t waves_per_cu;      /* persistent grid: CUs x waves_per_cu waves (4, 8, ...) */
     uint32_t use_graph;         /* capture planner + hash launches in a hipGraph */
-    uint32_t reserved;
+    uint32_t long_ring;         /* packets in flight per thread in the persistent
+                                   kernel: 24, 32, 48 or 64 */
 } hh_tuning;
 
 void hh_get_tuning(hh_tuning* t);

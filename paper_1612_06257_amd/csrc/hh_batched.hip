@@ -31,7 +31,6 @@
 namespace hh {
 
 constexpr int kBuckets = 256;
-constexpr int kLongRing = 24;  // packets in flight per thread in hh_long_kernel
 constexpr u64 kPriorityBytes = 64u << 10;  // items this long run at wave priority 3
 
 struct Plan {
@@ -129,24 +128,49 @@ __global__ __launch_bounds__(kBuckets) void hh_plan_scan_kernel(Plan* __restrict
     if (t == 0) plan->item_next = first_dynamic_item;
 }
 
+// Long list -> longest-first order.  Each block takes chunks of
+// kScatterPer*256 entries, ranks them per bucket in LDS and reserves one range
+// per bucket with a single global atomic.
+constexpr int kScatterPer = 4;
+
 __global__ __launch_bounds__(256) void hh_scatter_kernel(
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
     const u64* __restrict__ lengths, Plan* __restrict__ plan, const u32* __restrict__ long_list,
     u32* __restrict__ order) {
+    __shared__ u32 cnt[kBuckets];
+    __shared__ u32 base[kBuckets];
     const u32 n_long = plan->n_long;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n_long; i += gridDim.x * blockDim.x) {
-        const u32 j = long_list[i];
-        const Msg m = message(data, data_bytes, offsets[j], lengths[j]);
-        const u32 b = bucket_of(packets_capped(m.len));
-        const u32 pos = atomicAdd(&plan->cursor[b], 1u);
-        order[plan->start[b] + pos] = j;
+    const u32 chunk = kScatterPer * 256u;
+    for (u32 c0 = blockIdx.x * chunk; c0 < n_long; c0 += gridDim.x * chunk) {
+        for (u32 i = threadIdx.x; i < kBuckets; i += blockDim.x) cnt[i] = 0u;
+        __syncthreads();
+        u32 jj[kScatterPer], bk[kScatterPer], rk[kScatterPer];
+#pragma unroll
+        for (int k = 0; k < kScatterPer; ++k) {
+            const u32 i = c0 + (u32)k * 256u + threadIdx.x;
+            bk[k] = kBuckets;
+            if (i < n_long) {
+                jj[k] = long_list[i];
+                const Msg m = message(data, data_bytes, offsets[jj[k]], lengths[jj[k]]);
+                bk[k] = bucket_of(packets_capped(m.len));
+                rk[k] = atomicAdd(&cnt[bk[k]], 1u);
+            }
+        }
+        __syncthreads();
+        for (u32 b = threadIdx.x; b < kBuckets; b += blockDim.x)
+            if (cnt[b]) base[b] = plan->start[b] + atomicAdd(&plan->cursor[b], cnt[b]);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScatterPer; ++k)
+            if (bk[k] < kBuckets) order[base[bk[k]] + rk[k]] = jj[k];
+        __syncthreads();
     }
 }
 
 // Persistent: 16 messages per item, 4 threads per message.  Wave w (numbered
 // so that waves 0..gridDim.x-1 are the first waves of distinct workgroups)
 // takes item w first, then items from plan->item_next.
-template <int W>
+template <int W, int RING>
 __global__ __launch_bounds__(256) void hh_long_kernel(
     const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
@@ -172,7 +196,7 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
             const u32 j = order[k];
             const u64 key_q = keys[4 * key_index(key_idx, n_keys, j) + q];
             const Msg m = message(data, data_bytes, offsets[j], lengths[j]);
-            const u64 sum = hash_quad<kLongRing>(key_q, m.p, m.len, q);
+            const u64 sum = hash_quad<RING>(key_q, m.p, m.len, q);
             if (q < W) out[(u64)W * j + q] = sum;
         }
         u32 nxt = 0;
@@ -319,13 +343,22 @@ hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, co
                        (u64)tun.lane4_min_bytes, ws->plan, ws->long_list);
     hipLaunchKernelGGL(hh_plan_scan_kernel, dim3(1), dim3(kBuckets), 0, st, ws->plan,
                        long_blocks * 4u);
-    const unsigned scatter_blocks = (unsigned)std::min<u64>((a.n + 255) / 256, 1024);
+    const unsigned scatter_blocks =
+        (unsigned)std::min<u64>((a.n + kScatterPer * 256 - 1) / (kScatterPer * 256), 1024);
     hipLaunchKernelGGL(hh_scatter_kernel, dim3(scatter_blocks), dim3(256), 0, st, a.data,
                        a.data_bytes, a.offsets, a.lengths, ws->plan, ws->long_list, ws->order);
     EventPair* ev = timing_begin(st);
-    hipLaunchKernelGGL(hh_long_kernel<W>, dim3(long_blocks), dim3(256), lds, st, a.keys, a.n_keys,
-                       a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.out, ws->plan,
-                       ws->order);
+#define HH_LONG(RING)                                                                          \
+    hipLaunchKernelGGL((hh_long_kernel<W, RING>), dim3(long_blocks), dim3(256), lds, st, a.keys, \
+                       a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.out,  \
+                       ws->plan, ws->order)
+    switch (tun.long_ring) {
+        case 24: HH_LONG(24); break;
+        case 32: HH_LONG(32); break;
+        case 64: HH_LONG(64); break;
+        default: HH_LONG(48); break;
+    }
+#undef HH_LONG
     const bool ok = hipGetLastError() == hipSuccess;
     timing_end(ev, st);
     return ok ? HH_OK : HH_ERR_LAUNCH;

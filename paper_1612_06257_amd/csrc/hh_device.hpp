@@ -171,11 +171,14 @@ struct State1 {
 // Zipper result for this thread's lane: own dwords (L, H), partner's H = P.
 //   even lane: lo = L.3 P.0 L.2 H.1   hi = P.2 L.1 P.3 L.0
 //   odd lane:  lo = L.3 P.0 L.2 H.1   hi = L.1 P.2 L.0 P.3
+// C gathers this lane's three bytes of the low result dword without waiting
+// for the partner, so only one v_perm_b32 follows the DPP move on the
+// critical path.
 __device__ __forceinline__ u64 zipper1(u64 x, u32 sel_hi) {
     const u32 L = lo32(x), H = hi32(x);
     const u32 P = quad_swap1(H);
-    const u32 m = perm(P, H, 0x0c0c0104u);    // P.0 H.1 0 0
-    const u32 lo = perm(m, L, 0x05020403u);   // L.3 m.0 L.2 m.1
+    const u32 C = perm(H, L, 0x05020c03u);    // L.3 0 L.2 H.1
+    const u32 lo = perm(P, C, 0x03020400u);   // C.0 P.0 C.2 C.3
     const u32 hi = perm(P, L, sel_hi);
     return make64(lo, hi);
 }
@@ -236,127 +239,99 @@ __device__ __forceinline__ u32 remainder_dword(const u8* t, u32 r, u32 k) {
     return load_partial_le32(t + 4u * q4, r & 3u);
 }
 
-// Three aligned dwords covering one lane's 8 packet bytes.  `safe` selects
-// the third dword only when the bytes are misaligned (sh != 0), which keeps
-// the last packet's loads inside the message; otherwise dwords 0..2 are read
-// as one dwordx3 (the third then belongs to the following packet bytes).
-struct Dw3 {
-    u32 x, y, z;
-};
+// Unaligned loads.  The gfx950 memory path serves byte-aligned dword loads
+// (the HSA unaligned access mode the compiler itself relies on), so a lane's
+// 8 packet bytes are one global_load_dwordx2 of exactly those bytes.
+typedef u64 u64_any_align __attribute__((aligned(1)));
 
-__device__ __forceinline__ Dw3 load_dw3(const u32* d) {
-    Dw3 r;
-    r.x = d[0];
-    r.y = d[1];
-    r.z = d[2];
-    return r;
-}
-
-__device__ __forceinline__ Dw3 load_dw3_safe(const u32* d, u32 sh) {
-    Dw3 r;
-    r.x = d[0];
-    r.y = d[1];
-    r.z = d[sh ? 2 : 1];
-    return r;
-}
-
-__device__ __forceinline__ u64 lane_word(const Dw3& w, u32 sh) {
-    return make64(align_bytes(w.y, w.x, sh), align_bytes(w.z, w.y, sh));
-}
+__device__ __forceinline__ u64 load_le64(const u8* p) { return *(const u64_any_align*)p; }
 
 // Quad layout: absorb npk (>= 1) whole packets starting at the lane's bytes
-// lp (= message + 8q + 32*first).  A ring of D packets is kept in flight:
-// packet t+D is requested right after packet t is consumed.  All threads of
-// a quad run with the same npk.
-template <int D>
+// lp (= message + 8q + 32*first).  The packets in flight form two halves of
+// RING/2: while one half is consumed the other half's loads are in flight,
+// all issued at once, so every load gets half a ring of Updates of latency
+// cover even where the compiler waits for all outstanding loads at the loop
+// head.  All threads of a quad run with the same npk.
+template <int RING>
 __device__ __forceinline__ void absorb_quad(State1& s, const u8* lp, u32 npk) {
-    const u32 sh = misalignment(lp);
-    const u32* d = (const u32*)(lp - sh);
+    constexpr u32 H = RING / 2;
     const u32 last = npk - 1u;
-    Dw3 ring[D];
+    u64 A[H], B[H];
 #pragma unroll
-    for (int k = 0; k < D; ++k) ring[k] = load_dw3_safe(d + 8u * min((u32)k, last), sh);
+    for (u32 k = 0; k < H; ++k) A[k] = load_le64(lp + 32u * min(k, last));
     u32 t0 = 0;
-    // steady state: every requested packet is at most the second to last,
-    // so dwords 0..2 are inside the message
+    for (; t0 + 3u * H < npk; t0 += 2u * H) {
+        const u8* blk = lp + 32u * (t0 + H);
+#pragma unroll
+        for (u32 k = 0; k < H; ++k) B[k] = load_le64(blk + 32u * k);
+        // keep the loads here: the scheduler would otherwise sink them
+        // toward their uses and shorten the latency they are given
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (u32 k = 0; k < H; ++k) update1(s, A[k]);
+        blk += 32u * H;
+#pragma unroll
+        for (u32 k = 0; k < H; ++k) A[k] = load_le64(blk + 32u * k);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (u32 k = 0; k < H; ++k) update1(s, B[k]);
+    }
+    // drain: at most 3H packets remain, A holds the first H of them
+#pragma unroll
+    for (u32 k = 0; k < H; ++k) B[k] = load_le64(lp + 32u * min(t0 + H + k, last));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (u32 k = 0; k < H; ++k)
+        if (t0 + k < npk) update1(s, A[k]);
+#pragma unroll
+    for (u32 k = 0; k < H; ++k) A[k] = load_le64(lp + 32u * min(t0 + 2u * H + k, last));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (u32 k = 0; k < H; ++k)
+        if (t0 + H + k < npk) update1(s, B[k]);
+#pragma unroll
+    for (u32 k = 0; k < H; ++k)
+        if (t0 + 2u * H + k < npk) update1(s, A[k]);
+}
+
+// Thread layout: a packet is four unaligned 64-bit loads (two dwordx4).
+struct Packet {
+    u64 w[4];
+};
+
+__device__ __forceinline__ Packet load_packet(const u8* p) {
+    Packet r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.w[i] = load_le64(p + 8 * i);
+    return r;
+}
+
+template <int D>
+__device__ __forceinline__ void absorb_thread(State4& s, const u8* p, u32 npk) {
+    const u32 last = npk - 1u;
+    Packet ring[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) ring[k] = load_packet(p + 32u * min((u32)k, last));
+    u32 t0 = 0;
     for (; t0 + 2u * D < npk; t0 += D) {
-        const u32* blk = d + 8u * (t0 + D);
+        const u8* blk = p + 32u * (t0 + D);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            update1(s, lane_word(ring[k], sh));
-            ring[k] = load_dw3(blk + 8 * k);
+            update4(s, ring[k].w);
+            ring[k] = load_packet(blk + 32 * k);
         }
     }
-    // drain: fewer than 2D packets remain
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         if (t0 + k < npk) {
-            update1(s, lane_word(ring[k], sh));
-            ring[k] = load_dw3_safe(d + 8u * min(t0 + D + k, last), sh);
+            update4(s, ring[k].w);
+            ring[k] = load_packet(p + 32u * min(t0 + D + k, last));
         }
     }
     t0 += D;
 #pragma unroll
     for (int k = 0; k < D; ++k)
-        if (t0 + k < npk) update1(s, lane_word(ring[k], sh));
-}
-
-// Thread layout: 32 packet bytes at p as nine aligned dwords (the ninth only
-// read when p is misaligned).
-struct Dw9 {
-    u32 w[9];
-};
-
-__device__ __forceinline__ Dw9 load_dw9(const u32* d, u32 sh, bool safe) {
-    Dw9 r;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) r.w[k] = d[k];
-    r.w[8] = safe ? d[sh ? 8 : 7] : d[8];
-    return r;
-}
-
-__device__ __forceinline__ void packet_words(const Dw9& r, u32 sh, u64 pk[4]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        pk[i] = make64(align_bytes(r.w[2 * i + 1], r.w[2 * i], sh),
-                       align_bytes(r.w[2 * i + 2], r.w[2 * i + 1], sh));
-}
-
-template <int D>
-__device__ __forceinline__ void absorb_thread(State4& s, const u8* p, u32 npk) {
-    const u32 sh = misalignment(p);
-    const u32* d = (const u32*)(p - sh);
-    const u32 last = npk - 1u;
-    Dw9 ring[D];
-    u64 pk[4];
-#pragma unroll
-    for (int k = 0; k < D; ++k) ring[k] = load_dw9(d + 8u * min((u32)k, last), sh, true);
-    u32 t0 = 0;
-    for (; t0 + 2u * D < npk; t0 += D) {
-        const u32* blk = d + 8u * (t0 + D);
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            packet_words(ring[k], sh, pk);
-            update4(s, pk);
-            ring[k] = load_dw9(blk + 8 * k, sh, false);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        if (t0 + k < npk) {
-            packet_words(ring[k], sh, pk);
-            update4(s, pk);
-            ring[k] = load_dw9(d + 8u * min(t0 + D + k, last), sh, true);
-        }
-    }
-    t0 += D;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        if (t0 + k < npk) {
-            packet_words(ring[k], sh, pk);
-            update4(s, pk);
-        }
-    }
+        if (t0 + k < npk) update4(s, ring[k].w);
 }
 
 }  // namespace hh

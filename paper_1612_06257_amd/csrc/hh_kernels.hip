@@ -89,14 +89,15 @@ __global__ __launch_bounds__(256) void hh_state_step_kernel(
     for (u64 k = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 2; k < n; k += stride) {
         u64* st = states + 16 * (state_idx ? (u64)state_idx[k] : k);
         const Msg m = message(data, data_bytes, offsets[k], lengths[k]);
+        const u32 r = FINAL ? (u32)(m.len & 31u) : 0u;
+        const u64 tail = r ? remainder_lane(m.p + 32 * (m.len >> 5), r, q) : 0;
         State1 s;
         load_state1(s, st, q);
-        const u8* tail = absorb_quad_all<kQuadRing>(s, m.p, m.len >> 5, q);
+        absorb_quad_all<kQuadRing>(s, m.p, m.len >> 5, q);
         if (!FINAL) {
             store_state1(s, st, q);
         } else {
-            const u32 r = (u32)(m.len & 31u);
-            if (r) remainder1(s, tail, r, q);
+            if (r) remainder1(s, r, tail);
             const u64 sum = finalize1(s);
             const u32 w = width_words ? width_words[k] : 1u;
             const u64 o = out_offsets ? out_offsets[k] : 4 * k;

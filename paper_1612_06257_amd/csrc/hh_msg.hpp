@@ -25,37 +25,52 @@ __device__ __forceinline__ u64 key_index(const u32* key_idx, u32 n_keys, u64 j) 
     return k < n_keys ? k : n_keys - 1u;
 }
 
+// Sec. 4.5 padded remainder packet for the r (1..31) tail bytes at t, as four
+// lanes; loaded before the message's packets are absorbed so that its loads
+// overlap them.
+__device__ __forceinline__ void remainder_packet4(const u8* t, u32 r, u64 pk[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        pk[i] = make64(remainder_dword(t, r, 2 * i), remainder_dword(t, r, 2 * i + 1));
+}
+
 // Sec. 4.5 remainder step on a whole state held by one thread.
-__device__ __forceinline__ void remainder4(State4& s, const u8* tail, u32 r) {
+__device__ __forceinline__ void remainder4(State4& s, u32 r, const u64 pk[4]) {
     const u64 inject = ((u64)r << 32) + r;
-    u64 pk[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         s.v0[i] += inject;
         s.v1[i] = rotl_halves(s.v1[i], r);
-        pk[i] = make64(remainder_dword(tail, r, 2 * i), remainder_dword(tail, r, 2 * i + 1));
     }
     update4(s, pk);
 }
 
+// Lane q of the Sec. 4.5 padded remainder packet (quad layout).
+__device__ __forceinline__ u64 remainder_lane(const u8* t, u32 r, int q) {
+    return make64(remainder_dword(t, r, 2 * q), remainder_dword(t, r, 2 * q + 1));
+}
+
 // Sec. 4.5 remainder step, quad layout (thread holds lane q).
-__device__ __forceinline__ void remainder1(State1& s, const u8* tail, u32 r, int q) {
+__device__ __forceinline__ void remainder1(State1& s, u32 r, u64 lane_word) {
     s.v0 += ((u64)r << 32) + r;
     s.v1 = rotl_halves(s.v1, r);
-    update1(s, make64(remainder_dword(tail, r, 2 * q), remainder_dword(tail, r, 2 * q + 1)));
+    update1(s, lane_word);
 }
 
 // Packets per absorb call: lengths below 2^36 bytes need a single call.
 constexpr u64 kMaxPacketsPerCall = 1ull << 31;
 
-constexpr int kThreadRing = 2;  // packets in flight per thread (thread layout)
+constexpr int kThreadRing = 4;  // packets in flight per thread (thread layout)
 constexpr int kQuadRing = 8;    // packets in flight per thread (quad layout, wide grids)
 
 // The whole hash of one message in one thread; returns the final lane sums.
 __device__ __forceinline__ void hash_thread(const u64* key, const u8* p, u64 len, u64 sum[4]) {
+    const u32 r = (u32)(len & 31u);
+    u64 nfull = len >> 5;
+    u64 tail[4] = {0, 0, 0, 0};
+    if (r) remainder_packet4(p + 32 * nfull, r, tail);
     State4 s;
     reset4(s, key);
-    u64 nfull = len >> 5;
     const u8* cur = p;
     while (nfull) {
         const u32 npk = (u32)(nfull < kMaxPacketsPerCall ? nfull : kMaxPacketsPerCall);
@@ -63,8 +78,7 @@ __device__ __forceinline__ void hash_thread(const u64* key, const u8* p, u64 len
         cur += 32 * (u64)npk;
         nfull -= npk;
     }
-    const u32 r = (u32)(len & 31u);
-    if (r) remainder4(s, cur, r);
+    if (r) remainder4(s, r, tail);
     finalize4(s, sum);
 }
 
@@ -84,11 +98,13 @@ __device__ __forceinline__ const u8* absorb_quad_all(State1& s, const u8* p, u64
 // The whole hash of one message on a quad; returns lane q of the sums.
 template <int RING>
 __device__ __forceinline__ u64 hash_quad(u64 key_q, const u8* p, u64 len, int q) {
+    const u32 r = (u32)(len & 31u);
+    const u64 nfull = len >> 5;
+    const u64 tail = r ? remainder_lane(p + 32 * nfull, r, q) : 0;
     State1 s;
     reset1(s, key_q, q);
-    const u8* tail = absorb_quad_all<RING>(s, p, len >> 5, q);
-    const u32 r = (u32)(len & 31u);
-    if (r) remainder1(s, tail, r, q);
+    absorb_quad_all<RING>(s, p, nfull, q);
+    if (r) remainder1(s, r, tail);
     return finalize1(s);
 }
 

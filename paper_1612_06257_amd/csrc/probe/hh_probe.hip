@@ -45,6 +45,26 @@ __global__ __launch_bounds__(64) void hh_probe_chain_kernel(u32 n_updates, u32 p
     if (lane == 0) cycles[blockIdx.x] = t1 - t0;
 }
 
+// One wave absorbs 16 messages of npk packets each (4 threads per message)
+// straight from memory with the production packet loop.  Message m of wave w
+// starts at data + (16*w + m) * msg_bytes + misalign.
+template <int RING>
+__global__ __launch_bounds__(64) void hh_probe_absorb_kernel(const u8* __restrict__ data,
+                                                             u64 msg_bytes, u32 misalign, u32 npk,
+                                                             u64* __restrict__ cycles,
+                                                             u64* __restrict__ sink) {
+    const u32 lane = threadIdx.x;
+    const int q = (int)(lane & 3u);
+    const u8* p = data + (16ull * blockIdx.x + (lane >> 2)) * msg_bytes + misalign;
+    State1 s;
+    reset1(s, 0x9e3779b97f4a7c15ull * (lane + 1), q);
+    const u64 t0 = __builtin_amdgcn_s_memtime();
+    absorb_quad<RING>(s, p + 8 * q, npk);
+    const u64 t1 = __builtin_amdgcn_s_memtime();
+    sink[(u64)blockIdx.x * 64 + lane] = s.v0 ^ s.v1 ^ s.mul0 ^ s.mul1;
+    if (lane == 0) cycles[blockIdx.x] = t1 - t0;
+}
+
 // op kinds: 0 u64 add, 1 u32xu32->u64 multiply, 2 byte permute, 3 32-bit xor,
 // 4 DPP move, 5 alignbyte
 template <int OP>
@@ -107,6 +127,25 @@ int hh_probe_chain(int quad, u32 n_updates, u32 n_waves, u32 prio_waves, u64* cy
     else
         hipLaunchKernelGGL(hh_probe_chain_kernel<false>, dim3(n_waves), dim3(64), 0,
                            (hipStream_t)stream, n_updates, prio_waves, cycles, sink);
+    return hipGetLastError() == hipSuccess ? 0 : 4;
+}
+
+// data must hold 16 * n_waves * msg_bytes bytes; msg_bytes >= 32*npk + misalign + 12
+int hh_probe_absorb(int ring, const void* data, u64 data_bytes, u64 msg_bytes, u32 misalign,
+                    u32 npk, u32 n_waves, u64* cycles, u64* sink, void* stream) {
+    if (!data || !cycles || !sink || n_waves == 0 || npk == 0 || misalign > 3) return 1;
+    if (msg_bytes < 32ull * npk + misalign + 12 || 16ull * n_waves * msg_bytes > data_bytes) return 1;
+    hipStream_t st = (hipStream_t)stream;
+    const u8* d = (const u8*)data;
+    switch (ring) {
+        case 8: hipLaunchKernelGGL(hh_probe_absorb_kernel<8>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 16: hipLaunchKernelGGL(hh_probe_absorb_kernel<16>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 24: hipLaunchKernelGGL(hh_probe_absorb_kernel<24>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 32: hipLaunchKernelGGL(hh_probe_absorb_kernel<32>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 48: hipLaunchKernelGGL(hh_probe_absorb_kernel<48>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 64: hipLaunchKernelGGL(hh_probe_absorb_kernel<64>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        default: return 1;
+    }
     return hipGetLastError() == hipSuccess ? 0 : 4;
 }
 

@@ -40,7 +40,9 @@ def probe_lib() -> ctypes.CDLL:
     L.hh_probe_op_rate.argtypes = [ctypes.c_int, _u32, _u32, _vp, _vp]
     L.hh_probe_read.argtypes = [_vp, _u64, _u32, _vp, _vp]
     L.hh_probe_copy.argtypes = [_vp, _vp, _u64, _u32, _vp]
-    for f in ("hh_probe_chain", "hh_probe_op_rate", "hh_probe_read", "hh_probe_copy"):
+    L.hh_probe_absorb.argtypes = [ctypes.c_int, _vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp]
+    for f in ("hh_probe_chain", "hh_probe_op_rate", "hh_probe_read", "hh_probe_copy",
+              "hh_probe_absorb"):
         getattr(L, f).restype = ctypes.c_int
     return L
 
@@ -87,6 +89,29 @@ def chain(L, quad: bool, n_updates: int, n_waves: int, prio_waves: int = 0):
     return rec
 
 
+def absorb(L, ring: int, npk: int, n_waves: int, misalign: int, buf=None):
+    """Cycles per Update of the production quad packet loop reading memory."""
+    msg_bytes = 32 * npk + 64
+    need = 16 * n_waves * msg_bytes
+    if buf is None or buf.numel() < need:
+        buf = torch.empty(need, dtype=torch.uint8, device="cuda")
+        buf.fill_(0x5A)
+    cycles = torch.zeros(n_waves, dtype=torch.int64, device="cuda")
+    sink = torch.zeros(64 * n_waves, dtype=torch.int64, device="cuda")
+
+    def go():
+        rc = L.hh_probe_absorb(ring, _vp(buf.data_ptr()), buf.numel(), msg_bytes, misalign, npk,
+                               n_waves, _vp(cycles.data_ptr()), _vp(sink.data_ptr()), _stream())
+        assert rc == 0, rc
+
+    ms = _time(go, reps=3)
+    c = cycles.cpu().numpy().astype(np.float64) / npk
+    return {"kind": "absorb", "ring": ring, "npk": npk, "n_waves": n_waves,
+            "misalign": misalign, "kernel_ms": ms,
+            "cycles_per_update_median": float(np.median(c)),
+            "cycles_per_update_max": float(c.max())}, buf
+
+
 def op_rate(L, op: int, n_blocks: int = 2048, iters: int = 256):
     sink = torch.zeros(256 * n_blocks, dtype=torch.int64, device="cuda")
 
@@ -129,6 +154,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--json", default=None)
     ap.add_argument("--summary", default=None, help="write the key figures as JSON here")
+    ap.add_argument("--absorb", action="store_true", help="only the packet-loop probe")
     ap.add_argument("--copy-only", type=int, default=0,
                     help="only run the copy kernel on this many bytes (for counters)")
     args = ap.parse_args(argv)
@@ -140,6 +166,15 @@ def main(argv=None):
     props = torch.cuda.get_device_properties(0)
     cus = props.multi_processor_count
     recs = []
+    if args.absorb:
+        buf = None
+        for n_waves, npk in ((1, 32768), (4 * cus, 4096)):
+            for misalign in (0, 1):
+                for ring in (8, 16, 24, 32, 48, 64):
+                    r, buf = absorb(L, ring, npk, n_waves, misalign, buf)
+                    recs.append(r)
+                    print(json.dumps(r), flush=True)
+        return
     n_up = 20000
     for quad in (True, False):
         for n_waves in (1, cus, 4 * cus, 8 * cus, 16 * cus):
@@ -148,6 +183,12 @@ def main(argv=None):
         # priority: the first cus waves raise their priority, 16/CU in total
         recs.append(chain(L, quad, n_up, 16 * cus, prio_waves=cus))
         print(json.dumps(recs[-1]), flush=True)
+    buf = None
+    for ring in (16, 32, 64):
+        r, buf = absorb(L, ring, 32768, 1, 1, buf)
+        recs.append(r)
+        print(json.dumps(r), flush=True)
+    del buf
     for op in range(len(OPS)):
         recs.append(op_rate(L, op))
         print(json.dumps(recs[-1]), flush=True)
@@ -180,6 +221,10 @@ def summarize(recs, command: str) -> dict:
             out["op_rate_" + r["op"]] = r["lane_ops_per_s"]
         if r["kind"] == "read":
             out["hbm_read_GBps"] = r["GBps"]
+        if r["kind"] == "absorb" and r["n_waves"] == 1 and r["misalign"] == 1:
+            ns = r["kernel_ms"] * 1e6 / r["npk"]
+            out["quad_loop_ring%d_cycles_per_update" % r["ring"]] = r["cycles_per_update_median"]
+            out["quad_loop_ring%d_ns_per_update" % r["ring"]] = ns
     return out
 
 

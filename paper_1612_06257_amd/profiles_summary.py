@@ -34,11 +34,13 @@ def _per_kernel(path):
     return {k: sum(v) / len(v) for k, v in agg.items()}
 
 
-def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out, kernel="hh::hh_long_kernel<1>"):
+def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
+            kernel_prefix="hh::hh_long_kernel<1"):
     sys.path.insert(0, ".")
     import bench
     f = _per_kernel(fetch)
     w = _per_kernel(write)
+    kernel = next(k for k in f if k.startswith(kernel_prefix))
     cf = _per_kernel(copy_fetch)["hh::hh_probe_copy_kernel"]
     cw = _per_kernel(copy_write)["hh::hh_probe_copy_kernel"]
     f_factor = copy_bytes / (cf * 1024.0)
