@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void hh_state_step_kernel(
         const u64 tail = r ? remainder_lane(m.p + 32 * (m.len >> 5), r, q) : 0;
         State1 s;
         load_state1(s, st, q);
-        absorb_quad_all<kQuadRing>(s, m.p, m.len >> 5, q);
+        absorb_quad_all<kStateRing>(s, m.p, m.len >> 5, q);
         if (!FINAL) {
             store_state1(s, st, q);
         } else {

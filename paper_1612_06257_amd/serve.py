@@ -1,0 +1,438 @@
+"""Serving loop: continuous batching of hash requests on one GPU.
+
+A request is (key index, payload bytes, output width 1/2/4 words).  The loop
+keeps every admitted request's 1024-bit state and payload on the device and
+advances all of them together: each scheduler iteration gives every active
+request one chunk (a multiple of 32 bytes, or its whole remainder), launched
+as one streaming-state update and one finalization over all requests.  Only
+size mod 32 enters HighwayHash (Sec. 4.5 of the paper), so a long request
+resumes from its state each iteration and no length counter is kept.
+
+Requests that arrive while others are on the GPU are admitted as soon as a
+state slot and device memory (the admission budget: payload bytes rounded to
+256 plus 128 B of state and 32 B of output) are free, and join the next
+iteration.  The host runs one iteration ahead of the GPU and harvests
+completed iterations through events, so admission, chunk planning and
+launches overlap the device work.
+
+    python -m paper_1612_06257_amd.serve [--requests N] [--loads 0.25,0.5,0.8]
+
+prints one JSON line per load point: offered rate, GB/s, requests/s,
+p50/p90/p99 latency.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import dataclasses
+import json
+import sys
+import time
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+STATE_BYTES = 128
+OUT_BYTES = 32
+GRANULE = 256
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds from the start of the run
+    key_idx: int
+    width: int              # output words: 1, 2 or 4
+    length: int             # payload bytes
+    src: int                # payload offset in the source buffer
+    slot: int = -1          # state slot while admitted
+    arena_off: int = -1     # payload offset in the device arena
+    reserved: int = 0       # budget bytes held
+    pos: int = 0            # bytes already launched
+    final_launched: bool = False
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    result: Optional[Tuple[int, ...]] = None
+    status: str = "queued"  # queued, active, done, rejected
+
+
+class Arena:
+    """First-fit allocator over [0, capacity) in GRANULE units, coalescing."""
+
+    def __init__(self, capacity: int):
+        self.capacity = capacity // GRANULE * GRANULE
+        self.free: List[Tuple[int, int]] = [(0, self.capacity)]  # (offset, size), sorted
+        self.used = 0
+
+    def alloc(self, nbytes: int) -> Optional[int]:
+        n = max(GRANULE, (nbytes + GRANULE - 1) // GRANULE * GRANULE)
+        for i, (off, size) in enumerate(self.free):
+            if size >= n:
+                if size == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + n, size - n)
+                self.used += n
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int) -> None:
+        n = max(GRANULE, (nbytes + GRANULE - 1) // GRANULE * GRANULE)
+        self.used -= n
+        lo, hi = 0, len(self.free)
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if self.free[mid][0] < off:
+                lo = mid + 1
+            else:
+                hi = mid
+        self.free.insert(lo, (off, n))
+        # coalesce with neighbours
+        if lo + 1 < len(self.free) and self.free[lo][0] + self.free[lo][1] == self.free[lo + 1][0]:
+            self.free[lo] = (self.free[lo][0], self.free[lo][1] + self.free[lo + 1][1])
+            del self.free[lo + 1]
+        if lo > 0 and self.free[lo - 1][0] + self.free[lo - 1][1] == self.free[lo][0]:
+            self.free[lo - 1] = (self.free[lo - 1][0], self.free[lo - 1][1] + self.free[lo][1])
+            del self.free[lo]
+
+
+class GpuBackend:
+    """Device side of the loop: payload arena, states, outputs, launches.
+
+    source="device": the trace's payloads sit in a device ingress buffer and
+    admission copies them into the arena (device to device);
+    source="host": they sit in pinned host memory and admission copies them
+    host to device.  Copies run on their own stream; the compute stream waits
+    for them with an event.  Per-iteration item lists go through a ring of
+    pinned staging buffers so that no copy waits for the host."""
+
+    RING = 6  # staging sets; more than the scheduler's run-ahead + 1
+
+    def __init__(self, keys: np.ndarray, payload: np.ndarray, arena_bytes: int, max_slots: int,
+                 source: str = "device"):
+        import torch
+        from . import hh
+        self.torch, self.hh = torch, hh
+        hh.lib()
+        self.keys = torch.from_numpy(np.ascontiguousarray(keys)).view(torch.int64).cuda()
+        self.max_slots = max_slots
+        self.states = torch.zeros((max_slots, hh.STATE_WORDS), dtype=torch.int64, device="cuda")
+        self.out = torch.zeros((max_slots, 4), dtype=torch.int64, device="cuda")
+        self.arena = torch.empty(max(arena_bytes, GRANULE), dtype=torch.uint8, device="cuda")
+        self.source = source
+        src = torch.from_numpy(np.ascontiguousarray(payload))
+        if src.numel() == 0:
+            src = torch.zeros(1, dtype=torch.uint8)
+        if source == "device":
+            self.ingress = src.cuda()
+        else:
+            self.ingress = torch.empty(src.numel(), dtype=torch.uint8, pin_memory=True)
+            self.ingress.copy_(src)
+        self.copy_stream = torch.cuda.Stream()
+        self.compute_stream = torch.cuda.current_stream()
+        # item metadata layout per staging set (bytes): 2 x (offs u64, lens u64,
+        # out_offs u64, slots u32, widths u8) for updates and finals
+        self.meta_bytes = 2 * max_slots * (8 + 8 + 8 + 4 + 1) + 128
+        self.h_meta = [torch.empty(self.meta_bytes, dtype=torch.uint8, pin_memory=True)
+                       for _ in range(self.RING)]
+        self.d_meta = [torch.empty(self.meta_bytes, dtype=torch.uint8, device="cuda")
+                       for _ in range(self.RING)]
+        self.h_res = [torch.empty((max_slots, 4), dtype=torch.int64, pin_memory=True)
+                      for _ in range(self.RING)]
+        self.h_adm = [torch.empty(2 * max_slots * 4, dtype=torch.uint8, pin_memory=True)
+                      for _ in range(self.RING)]
+        self.d_adm = [torch.empty(2 * max_slots * 4, dtype=torch.uint8, device="cuda")
+                      for _ in range(self.RING)]
+        self.fresh = torch.zeros((max_slots, hh.STATE_WORDS), dtype=torch.int64, device="cuda")
+        self.k = 0
+        self.ka = 0
+
+    def admit(self, reqs: List[Request]) -> None:
+        """Copy the payloads of newly admitted requests into the arena and
+        reset their states."""
+        torch = self.torch
+        if not reqs:
+            return
+        with torch.cuda.stream(self.copy_stream):
+            for r in reqs:
+                if r.length:
+                    self.arena[r.arena_off:r.arena_off + r.length].copy_(
+                        self.ingress[r.src:r.src + r.length], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+        self.compute_stream.wait_event(ev)
+        n = len(reqs)
+        i = self.ka % self.RING
+        self.ka += 1
+        h = self.h_adm[i].numpy()
+        h[:4 * n].view(np.int32)[:] = [r.key_idx for r in reqs]
+        h[4 * n:8 * n].view(np.int32)[:] = [r.slot for r in reqs]
+        d = self.d_adm[i]
+        d[:8 * n].copy_(self.h_adm[i][:8 * n], non_blocking=True)
+        kidx = d[:4 * n].view(torch.int32)
+        slots = d[4 * n:8 * n].view(torch.int32)
+        fresh = self.hh.state_init(self.keys, n, kidx, self.fresh)
+        self.states.index_copy_(0, slots.long(), fresh[:n])
+
+    @staticmethod
+    def _put(h: np.ndarray, off: int, arr: np.ndarray, dt) -> Tuple[int, int]:
+        a = np.ascontiguousarray(arr, dtype=dt)
+        nb = a.nbytes
+        h[off:off + nb] = a.view(np.uint8)
+        return off, nb
+
+    def launch(self, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens, fin_widths):
+        """One iteration: fold whole-packet chunks into the states of
+        upd_slots, finish fin_slots.  Arrays of equal length per group.
+        Returns a ticket for done()/wait()/results()."""
+        torch, hh = self.torch, self.hh
+        i = self.k % self.RING
+        self.k += 1
+        h = self.h_meta[i].numpy()
+        regs = {}
+        off = 0
+        for name, arr, dt in (("uo", upd_offs, np.int64), ("ul", upd_lens, np.int64),
+                              ("us", upd_slots, np.int32), ("fo", fin_offs, np.int64),
+                              ("fl", fin_lens, np.int64), ("foo", 4 * np.asarray(fin_slots, np.int64), np.int64),
+                              ("fs", fin_slots, np.int32), ("fw", fin_widths, np.uint8)):
+            off = (off + 7) // 8 * 8
+            regs[name] = self._put(h, off, arr, dt)
+            off += regs[name][1]
+        d = self.d_meta[i]
+        d[:off].copy_(self.h_meta[i][:off], non_blocking=True)
+
+        def view(name, dt):
+            o, nb = regs[name]
+            return d[o:o + nb].view(dt)
+
+        n_upd, n_fin = len(upd_slots), len(fin_slots)
+        if n_upd:
+            hh.state_update(self.states, self.arena, view("uo", torch.int64),
+                            view("ul", torch.int64), view("us", torch.int32))
+        res = None
+        if n_fin:
+            slots = view("fs", torch.int32)
+            hh.state_final(self.states, self.arena, view("fo", torch.int64),
+                           view("fl", torch.int64), view("fw", torch.uint8),
+                           self.out.view(-1), view("foo", torch.int64), slots)
+            res = self.h_res[i][:n_fin]
+            res.copy_(self.out.index_select(0, slots.long()), non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(self.compute_stream)
+        return (ev, res)
+
+    def done(self, ticket) -> bool:
+        return ticket[0].query()
+
+    def wait(self, ticket) -> None:
+        ticket[0].synchronize()
+
+    def results(self, ticket) -> Optional[np.ndarray]:
+        """(n_fin, 4) uint64 hash words of the ticket's finished items, in the
+        order they were launched."""
+        ev, res = ticket
+        return None if res is None else res.numpy().view(np.uint64)
+
+
+class Server:
+    """Scheduler: admission under the budget, chunked continuous batching."""
+
+    def __init__(self, backend, budget_bytes: int, chunk_bytes: int = 1 << 16,
+                 max_active: Optional[int] = None, clock=time.perf_counter,
+                 sleep=time.sleep, run_ahead: int = 2):
+        if chunk_bytes <= 0 or chunk_bytes % 32:
+            raise ValueError("chunk_bytes must be a positive multiple of 32")
+        if run_ahead + 1 >= getattr(backend, "RING", 1 << 30):
+            raise ValueError("run_ahead too large for the backend's staging ring")
+        self.backend = backend
+        self.budget = budget_bytes
+        self.chunk = chunk_bytes
+        self.arena = Arena(budget_bytes)
+        self.max_active = max_active or backend.max_slots
+        self.free_slots = list(range(backend.max_slots))[::-1]
+        self.clock = clock
+        self.sleep = sleep
+        self.run_ahead = run_ahead
+        self.max_bytes_in_flight = 0
+
+    @staticmethod
+    def reservation(length: int) -> int:
+        return (max(length, 1) + GRANULE - 1) // GRANULE * GRANULE + STATE_BYTES + OUT_BYTES
+
+    def run(self, requests: List[Request]) -> dict:
+        """Serve `requests`.  Returns the run's metrics."""
+        waiting = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue: collections.deque = collections.deque()   # arrived, not admitted
+        S = self.backend.max_slots
+        # active set, indexed by state slot
+        busy = np.zeros(S, bool)          # admitted, final not yet launched
+        length = np.zeros(S, np.int64)
+        pos = np.zeros(S, np.int64)
+        base = np.zeros(S, np.int64)      # arena offset
+        width = np.zeros(S, np.uint8)
+        owner: List[Optional[Request]] = [None] * S
+        inflight: collections.deque = collections.deque()  # (ticket, finishing slots)
+        t0 = self.clock()
+        n_total = len(requests)
+        self.n_finished = 0
+        iterations = 0
+        self.reserved_bytes = 0
+        n_busy = 0
+
+        def harvest(block: bool) -> None:
+            ticket, fin = inflight.popleft()
+            if block:
+                self.backend.wait(ticket)
+            words = self.backend.results(ticket)
+            t = self.clock() - t0
+            for i, slot in enumerate(fin.tolist()):
+                r = owner[slot]
+                r.result = tuple(int(x) for x in words[i][:r.width])
+                r.t_done, r.status = t, "done"
+                self.arena.release(r.arena_off, max(r.length, 1))
+                self.reserved_bytes -= r.reserved
+                owner[slot] = None
+                self.free_slots.append(slot)
+                self.n_finished += 1
+
+        while self.n_finished < n_total:
+            now = self.clock() - t0
+            while waiting and waiting[0].arrival <= now:
+                queue.append(waiting.popleft())
+            # admission, in arrival order, while a slot and budget are free
+            admitted = []
+            while queue and self.free_slots and n_busy < self.max_active:
+                r = queue[0]
+                need = self.reservation(r.length)
+                if need > self.budget:
+                    queue.popleft()
+                    r.status, r.t_done = "rejected", now
+                    self.n_finished += 1
+                    continue
+                if self.reserved_bytes + need > self.budget:
+                    break  # back-pressure: wait for completions
+                off = self.arena.alloc(max(r.length, 1))
+                if off is None:
+                    break  # fragmented: wait for completions
+                queue.popleft()
+                slot = self.free_slots.pop()
+                r.arena_off, r.slot, r.reserved = off, slot, need
+                r.status, r.t_admit = "active", now
+                self.reserved_bytes += need
+                busy[slot], length[slot], pos[slot] = True, r.length, 0
+                base[slot], width[slot], owner[slot] = off, r.width, r
+                n_busy += 1
+                admitted.append(r)
+            self.max_bytes_in_flight = max(self.max_bytes_in_flight, self.reserved_bytes)
+            self.backend.admit(admitted)
+            # one chunk for every busy request: whole packets, or its final rest
+            launched = False
+            if n_busy:
+                idx = np.flatnonzero(busy)
+                rem = length[idx] - pos[idx]
+                fin = rem <= self.chunk
+                u, f = idx[~fin], idx[fin]
+                ticket = self.backend.launch(u, base[u] + pos[u], np.full(u.size, self.chunk),
+                                             f, base[f] + pos[f], rem[fin], width[f])
+                pos[u] += self.chunk
+                pos[f] = length[f]
+                busy[f] = False
+                n_busy -= f.size
+                inflight.append((ticket, f))
+                iterations += 1
+                launched = True
+            # harvest what has finished; block when too far ahead or idle
+            while inflight and self.backend.done(inflight[0][0]):
+                harvest(False)
+            while len(inflight) > self.run_ahead:
+                harvest(True)
+            if not launched and inflight:
+                harvest(True)
+            if not n_busy and not inflight and not queue and waiting:
+                self.sleep(max(0.0, min(1e-3, waiting[0].arrival - (self.clock() - t0))))
+        t_end = self.clock() - t0
+        return self.metrics(requests, t_end, iterations)
+
+    def metrics(self, requests: List[Request], t_end: float, iterations: int) -> dict:
+        done = [r for r in requests if r.status == "done"]
+        lat = np.array([r.t_done - r.arrival for r in done]) if done else np.zeros(1)
+        nbytes = sum(r.length for r in done)
+        first = min((r.arrival for r in requests), default=0.0)
+        span = max(t_end - first, 1e-9)
+        return {
+            "requests": len(requests), "completed": len(done),
+            "rejected": sum(r.status == "rejected" for r in requests),
+            "bytes": nbytes, "seconds": span, "GBps": nbytes / span / 1e9,
+            "requests_per_s": len(done) / span,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p90_ms": float(np.percentile(lat, 90) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "iterations": iterations,
+            "chunk_bytes": self.chunk, "budget_bytes": self.budget,
+            "max_bytes_in_flight": self.max_bytes_in_flight,
+        }
+
+
+def requests_from_trace(trace) -> List[Request]:
+    return [Request(rid=i, arrival=float(trace.arrival_s[i]), key_idx=int(trace.key_idx[i]),
+                    width=int(trace.width_words[i]), length=int(trace.lengths[i]),
+                    src=int(trace.offsets[i])) for i in range(trace.n)]
+
+
+def serve_trace(trace, budget_bytes: int = 32 << 30, chunk_bytes: int = 1 << 16,
+                max_slots: int = 4096, source: str = "device", time_scale: float = 1.0):
+    """Run one trace on the GPU; returns (metrics, requests)."""
+    reqs = requests_from_trace(trace)
+    for r in reqs:
+        r.arrival *= time_scale
+    arena = min(budget_bytes, max(GRANULE, sum(Server.reservation(r.length) for r in reqs)))
+    backend = GpuBackend(trace.keys, trace.data, arena, max_slots, source)
+    server = Server(backend, budget_bytes=arena if arena < budget_bytes else budget_bytes,
+                    chunk_bytes=chunk_bytes)
+    m = server.run(reqs)
+    m["budget_bytes"] = budget_bytes
+    m["source"] = source
+    return m, reqs
+
+
+def load_sweep(n_requests: int = 10000, loads=(0.25, 0.5, 0.8), chunk_bytes: int = 1 << 16,
+               budget_bytes: int = 32 << 30, source: str = "device", seed: Optional[int] = None):
+    """Saturation run (every request arrives at t=0), then Poisson loads at
+    the given fractions of the measured saturation request rate."""
+    from . import workloads as W
+    kw = {} if seed is None else {"seed": seed}
+    base = W.serving_trace(n_requests, 1.0, **kw)
+    base.arrival_s[:] = 0.0
+    sat, _ = serve_trace(base, budget_bytes, chunk_bytes, source=source)
+    sat_rate = sat["requests_per_s"]
+    out = [dict(sat, load="saturation", offered_requests_per_s=None)]
+    for f in loads:
+        tr = W.serving_trace(n_requests, f * sat_rate, materialize=False, **kw)
+        tr.data, tr.offsets, tr.lengths = base.data, base.offsets, base.lengths
+        tr.key_idx, tr.width_words, tr.keys = base.key_idx, base.width_words, base.keys
+        m, _ = serve_trace(tr, budget_bytes, chunk_bytes, source=source)
+        out.append(dict(m, load=f, offered_requests_per_s=f * sat_rate))
+    return out
+
+
+def bench_summary(n_requests: int = 2000, load: float = 0.5, chunk_bytes: int = 1 << 16) -> dict:
+    """Short run for the benchmark line: saturation plus one Poisson load."""
+    pts = load_sweep(n_requests, (load,), chunk_bytes)
+    return {"saturation": pts[0], "load": pts[1]}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--loads", default="0.25,0.5,0.8")
+    ap.add_argument("--chunk", type=int, default=1 << 16)
+    ap.add_argument("--budget-gib", type=float, default=32.0)
+    ap.add_argument("--source", default="device", choices=["device", "host"])
+    args = ap.parse_args(argv)
+    loads = tuple(float(x) for x in args.loads.split(",") if x)
+    for p in load_sweep(args.requests, loads, args.chunk, int(args.budget_gib * 2**30), args.source):
+        print(json.dumps(p), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

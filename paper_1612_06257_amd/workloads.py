@@ -149,7 +149,9 @@ def power_law_lengths(rng: np.random.Generator, n: int, s: float = 1.1, lo: int 
                       hi: int = 2**24) -> np.ndarray:
     """Bounded power law: a continuous density proportional to x^-s on
     [lo, hi+1), floored to an integer (a Zipf(s) law on lo..hi up to the
-    discretisation)."""
+    discretisation).  Requires lo >= 1."""
+    if lo < 1:
+        raise ValueError("lo must be at least 1")
     u = rng.random(n)
     a = float(lo) ** (1.0 - s)
     b = float(hi + 1) ** (1.0 - s)

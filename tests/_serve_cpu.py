@@ -1,0 +1,77 @@
+"""A CPU stand-in for the serving loop's GPU backend (test infrastructure).
+
+It keeps a byte arena exactly like the device backend, streams every request
+through the oracle's incremental hasher, checks that admitted payload regions
+never overlap, and advances a virtual clock by a simple cost model so that the
+scheduler can be exercised without a GPU."""
+import numpy as np
+
+import oracle
+
+
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-6)
+
+
+class CpuBackend:
+    RING = 1 << 30
+
+    def __init__(self, keys, payload, arena_bytes, max_slots, clock, ns_per_byte=0.05,
+                 launch_s=20e-6):
+        self.keys = np.asarray(keys, np.uint64).reshape(-1, 4)
+        self.payload = payload
+        self.arena = np.zeros(max(arena_bytes, 256), np.uint8)
+        self.max_slots = max_slots
+        self.clock = clock
+        self.ns_per_byte = ns_per_byte
+        self.launch_s = launch_s
+        self.cats = {}
+        self.live = {}   # slot -> (arena_off, length)
+        self.launches = 0
+
+    def _check_no_overlap(self):
+        spans = sorted((o, o + max(n, 1)) for o, n in self.live.values())
+        for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
+            assert a1 <= b0, "arena regions overlap"
+
+    def admit(self, reqs):
+        for r in reqs:
+            assert r.slot not in self.cats, "slot reused while live"
+            self.arena[r.arena_off:r.arena_off + r.length] = self.payload[r.src:r.src + r.length]
+            self.cats[r.slot] = oracle.Cat(self.keys[r.key_idx])
+            self.live[r.slot] = (r.arena_off, r.length)
+        self._check_no_overlap()
+
+    def launch(self, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens, fin_widths):
+        self.launches += 1
+        biggest = 0
+        for slot, off, n in zip(upd_slots.tolist(), upd_offs.tolist(), upd_lens.tolist()):
+            assert n % 32 == 0
+            self.cats[slot].append(self.arena[off:off + n])
+            biggest = max(biggest, n)
+        res = np.zeros((len(fin_slots), 4), np.uint64)
+        for i, (slot, off, n) in enumerate(zip(fin_slots.tolist(), fin_offs.tolist(),
+                                               fin_lens.tolist())):
+            c = self.cats.pop(slot)
+            c.append(self.arena[off:off + n])
+            res[i] = c.finish(4)
+            del self.live[slot]
+            biggest = max(biggest, n)
+        self.clock.t += self.launch_s + biggest * self.ns_per_byte * 1e-9
+        return res
+
+    def done(self, ticket):
+        return True
+
+    def wait(self, ticket):
+        pass
+
+    def results(self, ticket):
+        return ticket

@@ -1,0 +1,95 @@
+"""The serving scheduler on a CPU stand-in backend: continuous batching gives
+every request the same hash as hashing it alone, admission never exceeds the
+budget, oversized requests are refused, and the arena allocator never hands
+out overlapping regions."""
+import numpy as np
+import pytest
+
+import oracle
+from _serve_cpu import CpuBackend, VirtualClock
+from paper_1612_06257_amd import serve, workloads
+
+
+def _trace(n, rate, hi, seed=7):
+    tr = workloads.serving_trace(n, rate, lo=1, hi=hi, n_keys=8, seed=seed)
+    tr.lengths[::17] = 0  # some empty requests
+    return tr
+
+
+def _run(tr, budget, chunk, max_slots=64):
+    clock = VirtualClock()
+    reqs = serve.requests_from_trace(tr)
+    arena = budget
+    be = CpuBackend(tr.keys, tr.data, arena, max_slots, clock)
+    srv = serve.Server(be, budget_bytes=budget, chunk_bytes=chunk, clock=clock, sleep=clock.sleep)
+    m = srv.run(reqs)
+    return m, reqs, be
+
+
+def test_arena_allocator_no_overlap_and_coalesces():
+    rng = np.random.default_rng(1)
+    a = serve.Arena(1 << 20)
+    live = {}
+    for step in range(2000):
+        if live and (rng.random() < 0.45 or len(live) > 50):
+            k = list(live)[int(rng.integers(0, len(live)))]
+            off, n = live.pop(k)
+            a.release(off, n)
+        else:
+            n = int(rng.integers(1, 40000))
+            off = a.alloc(n)
+            if off is not None:
+                for o2, n2 in live.values():
+                    r1 = (off, off + (n + 255) // 256 * 256)
+                    r2 = (o2, o2 + (n2 + 255) // 256 * 256)
+                    assert r1[1] <= r2[0] or r2[1] <= r1[0]
+                live[step] = (off, n)
+    for off, n in live.values():
+        a.release(off, n)
+    assert a.free == [(0, a.capacity)] and a.used == 0
+
+
+@pytest.mark.parametrize("chunk", [32, 256, 4096])
+def test_results_equal_one_shot_hashes(chunk):
+    tr = _trace(250, 2000.0, hi=6000)
+    m, reqs, be = _run(tr, budget=1 << 16, chunk=chunk)
+    assert m["completed"] + m["rejected"] == len(reqs)
+    assert m["rejected"] == 0
+    for r in reqs:
+        msg = tr.data[r.src:r.src + r.length]
+        assert r.result == tuple(oracle.hash_words(tr.keys[r.key_idx], msg, r.width)), r.rid
+    assert m["max_bytes_in_flight"] <= 1 << 16
+    assert be.launches == m["iterations"]
+
+
+def test_admission_respects_budget_and_back_pressure():
+    tr = _trace(200, 1e6, hi=20000, seed=3)   # everything arrives at once
+    budget = 40000
+    m, reqs, be = _run(tr, budget=budget, chunk=512)
+    assert m["max_bytes_in_flight"] <= budget
+    big = [r for r in reqs if serve.Server.reservation(r.length) > budget]
+    assert all(r.status == "rejected" for r in big)
+    assert all(r.status == "done" for r in reqs if r not in big)
+    for r in reqs:
+        if r.status == "done":
+            msg = tr.data[r.src:r.src + r.length]
+            assert r.result == tuple(oracle.hash_words(tr.keys[r.key_idx], msg, r.width))
+
+
+def test_result_alone_equals_result_in_mix():
+    tr = _trace(60, 500.0, hi=3000, seed=11)
+    m, reqs, _ = _run(tr, budget=1 << 15, chunk=64)
+    for r in reqs[:12]:
+        solo = workloads.Trace(tr.seed, tr.rate, np.zeros(1), tr.keys,
+                               np.array([r.key_idx], np.uint32), np.array([r.width], np.uint8),
+                               tr.data, np.array([r.src], np.uint64),
+                               np.array([r.length], np.uint64))
+        m1, reqs1, _ = _run(solo, budget=1 << 15, chunk=64)
+        assert reqs1[0].result == r.result
+
+
+def test_chunk_must_be_packet_multiple():
+    clock = VirtualClock()
+    be = CpuBackend(np.zeros((1, 4), np.uint64), np.zeros(0, np.uint8), 1024, 4, clock)
+    with pytest.raises(ValueError):
+        serve.Server(be, budget_bytes=1024, chunk_bytes=100)
