@@ -171,7 +171,8 @@ void hh_get_tuning(hh_tuning* t) {
 }
 
 hh_status hh_set_tuning(const hh_tuning* t) {
-    if (!t || t->waves_per_cu == 0 || t->waves_per_cu > 32) return HH_ERR_INVALID_ARG;
+    if (!t || t->waves_per_cu == 0 || t->waves_per_cu > 32 || t->use_graph > 1)
+        return HH_ERR_INVALID_ARG;
     if (t->long_ring != 24 && t->long_ring != 32 && t->long_ring != 48 && t->long_ring != 64)
         return HH_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(hh::g_mutex);

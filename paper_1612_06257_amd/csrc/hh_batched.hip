@@ -9,13 +9,15 @@
 // that every long chain owns its SIMD's issue slots and the longest chains
 // start first (longest-processing-time-first list scheduling).
 //
-// Launch sequence on one stream (all device-side, no host synchronisation):
+// Launch sequence on one stream (all device-side, no host synchronisation;
+// optionally captured once per argument set into a hipGraph and replayed):
 //   hh_plan_reset_kernel   zero the plan counters
 //   hh_split_kernel<W>     L < threshold: hash in-thread;  else: append the
 //                          index to the long list and count it in its length
 //                          bucket (8 buckets per octave of the packet count)
-//   hh_plan_scan_kernel    bucket start offsets, longest bucket first
-//   hh_scatter_kernel      long list -> bucket order
+//   hh_scatter_kernel      bucket start offsets (longest bucket first, every
+//                          block recomputes the 256-entry prefix), then long
+//                          list -> bucket order
 //   hh_long_kernel<W>      persistent: wave w first takes item w (16 messages,
 //                          4 threads each), then items from an atomic counter
 // Messages inside a bucket come out in any order; each message's result only
@@ -38,13 +40,13 @@ struct Plan {
     u32 item_next;  // next dynamic item of hh_long_kernel
     u32 pad[2];
     u32 hist[kBuckets];
-    u32 start[kBuckets];
     u32 cursor[kBuckets];
 };
 
-// length bucket of a message with npk >= 1 whole packets: 8 per octave,
-// increasing with npk
+// length bucket of a message with npk whole packets: 8 per octave,
+// increasing with npk (messages without a whole packet share bucket 0)
 __device__ __forceinline__ u32 bucket_of(u32 npk) {
+    npk = npk ? npk : 1u;
     const u32 lz = 31u - (u32)__clz(npk);
     const u32 sub = lz >= 3u ? (npk >> (lz - 3u)) & 7u : (npk << (3u - lz)) & 7u;
     return lz * 8u + sub;
@@ -55,9 +57,12 @@ __device__ __forceinline__ u32 packets_capped(u64 len) {
     return npk > 0xffffffffull ? 0xffffffffu : (u32)npk;
 }
 
-__global__ __launch_bounds__(256) void hh_plan_reset_kernel(Plan* __restrict__ plan) {
+__global__ __launch_bounds__(256) void hh_plan_reset_kernel(Plan* __restrict__ plan,
+                                                            u32 first_dynamic_item) {
     u32* w = (u32*)plan;
     for (u32 i = threadIdx.x; i < sizeof(Plan) / 4; i += blockDim.x) w[i] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) plan->item_next = first_dynamic_item;
 }
 
 template <int W>
@@ -108,41 +113,38 @@ __global__ __launch_bounds__(256) void hh_split_kernel(
         if (hist[i]) atomicAdd(&plan->hist[i], hist[i]);
 }
 
-// one block of kBuckets threads: exclusive prefix over buckets, longest first
-__global__ __launch_bounds__(kBuckets) void hh_plan_scan_kernel(Plan* __restrict__ plan,
-                                                                u32 first_dynamic_item) {
-    __shared__ u32 s[kBuckets];
-    const u32 t = threadIdx.x;
-    const u32 b = kBuckets - 1u - t;  // t = 0 is the longest bucket
-    const u32 c = plan->hist[b];
-    s[t] = c;
-    __syncthreads();
-    for (u32 d = 1; d < kBuckets; d <<= 1) {
-        const u32 v = t >= d ? s[t - d] : 0u;
-        __syncthreads();
-        s[t] += v;
-        __syncthreads();
-    }
-    plan->start[b] = s[t] - c;
-    plan->cursor[b] = 0u;
-    if (t == 0) plan->item_next = first_dynamic_item;
-}
-
 // Long list -> longest-first order.  Each block takes chunks of
 // kScatterPer*256 entries, ranks them per bucket in LDS and reserves one range
 // per bucket with a single global atomic.
 constexpr int kScatterPer = 4;
 
-__global__ __launch_bounds__(256) void hh_scatter_kernel(
+__global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
     const u64* __restrict__ lengths, Plan* __restrict__ plan, const u32* __restrict__ long_list,
     u32* __restrict__ order) {
     __shared__ u32 cnt[kBuckets];
     __shared__ u32 base[kBuckets];
+    __shared__ u32 start[kBuckets];
+    // bucket starts: exclusive prefix over buckets, longest bucket first
+    {
+        const u32 t = threadIdx.x;
+        const u32 b = kBuckets - 1u - t;
+        const u32 c = plan->hist[b];
+        cnt[t] = c;
+        __syncthreads();
+        for (u32 d = 1; d < kBuckets; d <<= 1) {
+            const u32 v = t >= d ? cnt[t - d] : 0u;
+            __syncthreads();
+            cnt[t] += v;
+            __syncthreads();
+        }
+        start[b] = cnt[t] - c;
+        __syncthreads();
+    }
     const u32 n_long = plan->n_long;
     const u32 chunk = kScatterPer * 256u;
     for (u32 c0 = blockIdx.x * chunk; c0 < n_long; c0 += gridDim.x * chunk) {
-        for (u32 i = threadIdx.x; i < kBuckets; i += blockDim.x) cnt[i] = 0u;
+        cnt[threadIdx.x] = 0u;
         __syncthreads();
         u32 jj[kScatterPer], bk[kScatterPer], rk[kScatterPer];
 #pragma unroll
@@ -157,8 +159,10 @@ __global__ __launch_bounds__(256) void hh_scatter_kernel(
             }
         }
         __syncthreads();
-        for (u32 b = threadIdx.x; b < kBuckets; b += blockDim.x)
-            if (cnt[b]) base[b] = plan->start[b] + atomicAdd(&plan->cursor[b], cnt[b]);
+        {
+            const u32 b = threadIdx.x;
+            if (cnt[b]) base[b] = start[b] + atomicAdd(&plan->cursor[b], cnt[b]);
+        }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kScatterPer; ++k)
@@ -244,17 +248,9 @@ EventPair* timing_begin(hipStream_t st) {
         (void)hipGetLastError();
         return nullptr;
     }
-    if (hipEventRecord(p.start, st) != hipSuccess) {
-        (void)hipGetLastError();
-        g_timing_pool.push_back(p);
-        return nullptr;
-    }
+    (void)st;
     g_timing_pending.push_back(p);
     return &g_timing_pending.back();
-}
-
-void timing_end(EventPair* p, hipStream_t st) {
-    if (p && hipEventRecord(p->stop, st) != hipSuccess) (void)hipGetLastError();
 }
 
 struct DeviceInfo {
@@ -287,6 +283,8 @@ DeviceInfo device_info(int dev) {
 
 u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
 
+void drop_graphs_of(const u8* ws_mem);
+
 hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out) {
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     Workspace* ws = nullptr;
@@ -305,12 +303,18 @@ hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out) {
         if (ws->mem) {
             // earlier work on this stream may still read the old buffers
             if (hipStreamSynchronize(st) != hipSuccess) return HH_ERR_LAUNCH;
+            drop_graphs_of(ws->mem);
             (void)hipFree(ws->mem);
             ws->mem = nullptr;
             ws->cap_msgs = 0;
         }
         if (hipMalloc(&mem, plan_bytes + 2 * list_bytes) != hipSuccess) {
             (void)hipGetLastError();
+            return HH_ERR_OUT_OF_MEMORY;
+        }
+        if (hipMemset(mem, 0, plan_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(mem);
             return HH_ERR_OUT_OF_MEMORY;
         }
         ws->mem = mem;
@@ -323,35 +327,48 @@ hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out) {
     return HH_OK;
 }
 
-template <int W>
-hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, const DeviceInfo& di,
-                            const hh_tuning& tun) {
+struct LaunchShape {
+    u32 long_blocks;
+    u32 lds;
+    unsigned split_blocks;
+    unsigned scatter_blocks;
+};
+
+LaunchShape launch_shape(const HashArgs& a, const DeviceInfo& di, const hh_tuning& tun) {
+    LaunchShape ls;
     const u32 waves_per_cu = tun.waves_per_cu ? tun.waves_per_cu : 4u;
     const u32 blocks_per_cu = (waves_per_cu + 3u) / 4u;
-    const u32 long_blocks = (u32)di.cus * blocks_per_cu;
+    ls.long_blocks = (u32)di.cus * blocks_per_cu;
     // LDS per workgroup so that only blocks_per_cu workgroups fit on a CU
-    u32 lds = 0;
+    ls.lds = 0;
     if (di.lds_per_cu > 0) {
-        lds = (u32)di.lds_per_cu / (blocks_per_cu + 1u) + 1024u;
-        if (di.lds_per_block > 0 && lds > (u32)di.lds_per_block) lds = (u32)di.lds_per_block;
-        lds &= ~255u;
+        ls.lds = (u32)di.lds_per_cu / (blocks_per_cu + 1u) + 1024u;
+        if (di.lds_per_block > 0 && ls.lds > (u32)di.lds_per_block) ls.lds = (u32)di.lds_per_block;
+        ls.lds &= ~255u;
     }
-    const unsigned split_blocks = (unsigned)std::min<u64>((a.n + 255) / 256, 8192);
-    hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan);
-    hipLaunchKernelGGL(hh_split_kernel<W>, dim3(split_blocks), dim3(256), 0, st, a.keys, a.n_keys,
-                       a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.n, a.out,
-                       (u64)tun.lane4_min_bytes, ws->plan, ws->long_list);
-    hipLaunchKernelGGL(hh_plan_scan_kernel, dim3(1), dim3(kBuckets), 0, st, ws->plan,
-                       long_blocks * 4u);
-    const unsigned scatter_blocks =
+    ls.split_blocks = (unsigned)std::min<u64>((a.n + 255) / 256, 8192);
+    ls.scatter_blocks =
         (unsigned)std::min<u64>((a.n + kScatterPer * 256 - 1) / (kScatterPer * 256), 1024);
-    hipLaunchKernelGGL(hh_scatter_kernel, dim3(scatter_blocks), dim3(256), 0, st, a.data,
+    return ls;
+}
+
+// The four launches of one bucketed call.  `ev` (may be null) brackets the
+// persistent kernel for the measurement hook.
+template <int W>
+void enqueue_sequence(const HashArgs& a, hipStream_t st, const Workspace* ws,
+                      const LaunchShape& ls, const hh_tuning& tun, EventPair* ev) {
+    hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan,
+                       ls.long_blocks * 4u);
+    hipLaunchKernelGGL(hh_split_kernel<W>, dim3(ls.split_blocks), dim3(256), 0, st, a.keys,
+                       a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.n, a.out,
+                       (u64)tun.lane4_min_bytes, ws->plan, ws->long_list);
+    hipLaunchKernelGGL(hh_scatter_kernel, dim3(ls.scatter_blocks), dim3(kBuckets), 0, st, a.data,
                        a.data_bytes, a.offsets, a.lengths, ws->plan, ws->long_list, ws->order);
-    EventPair* ev = timing_begin(st);
-#define HH_LONG(RING)                                                                          \
-    hipLaunchKernelGGL((hh_long_kernel<W, RING>), dim3(long_blocks), dim3(256), lds, st, a.keys, \
-                       a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.out,  \
-                       ws->plan, ws->order)
+    if (ev && hipEventRecord(ev->start, st) != hipSuccess) (void)hipGetLastError();
+#define HH_LONG(RING)                                                                        \
+    hipLaunchKernelGGL((hh_long_kernel<W, RING>), dim3(ls.long_blocks), dim3(256), ls.lds, st, \
+                       a.keys, a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, \
+                       a.out, ws->plan, ws->order)
     switch (tun.long_ring) {
         case 24: HH_LONG(24); break;
         case 32: HH_LONG(32); break;
@@ -359,9 +376,100 @@ hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, co
         default: HH_LONG(48); break;
     }
 #undef HH_LONG
-    const bool ok = hipGetLastError() == hipSuccess;
-    timing_end(ev, st);
-    return ok ? HH_OK : HH_ERR_LAUNCH;
+    if (ev && hipEventRecord(ev->stop, st) != hipSuccess) (void)hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// hipGraph cache: one instantiated graph per (stream, arguments, tuning,
+// workspace), least recently used evicted beyond kMaxGraphs.
+
+struct GraphEntry {
+    HashArgs a;
+    hipStream_t st;
+    hh_tuning tun;
+    const u8* ws_mem;
+    u64 ws_cap;
+    hipGraphExec_t exec;
+    u64 last_use;
+};
+
+constexpr size_t kMaxGraphs = 16;
+std::mutex g_graph_mutex;
+std::vector<GraphEntry> g_graphs;
+u64 g_graph_clock = 0;
+
+bool same_call(const GraphEntry& e, const HashArgs& a, hipStream_t st, const hh_tuning& t,
+               const Workspace* ws) {
+    return e.st == st && e.ws_mem == ws->mem && e.ws_cap == ws->cap_msgs && e.a.keys == a.keys &&
+           e.a.n_keys == a.n_keys && e.a.key_idx == a.key_idx && e.a.data == a.data &&
+           e.a.data_bytes == a.data_bytes && e.a.offsets == a.offsets &&
+           e.a.lengths == a.lengths && e.a.n == a.n && e.a.out == a.out && e.a.width == a.width &&
+           e.tun.lane4_min_bytes == t.lane4_min_bytes && e.tun.waves_per_cu == t.waves_per_cu &&
+           e.tun.long_ring == t.long_ring;
+}
+
+void drop_graphs_of(const u8* ws_mem) {
+    std::lock_guard<std::mutex> lock(g_graph_mutex);
+    for (size_t i = 0; i < g_graphs.size();) {
+        if (g_graphs[i].ws_mem == ws_mem) {
+            (void)hipGraphExecDestroy(g_graphs[i].exec);
+            g_graphs.erase(g_graphs.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+template <int W>
+hh_status launch_graph(const HashArgs& a, hipStream_t st, const Workspace* ws, const LaunchShape& ls,
+                       const hh_tuning& tun) {
+    std::lock_guard<std::mutex> lock(g_graph_mutex);
+    for (auto& e : g_graphs) {
+        if (same_call(e, a, st, tun, ws)) {
+            e.last_use = ++g_graph_clock;
+            return hipGraphLaunch(e.exec, st) == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return HH_ERR_LAUNCH;
+    }
+    enqueue_sequence<W>(a, st, ws, ls, tun, nullptr);
+    const hipError_t launch_err = hipGetLastError();
+    const hipError_t end_err = hipStreamEndCapture(st, &graph);
+    if (launch_err != hipSuccess || end_err != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return HH_ERR_LAUNCH;
+    }
+    const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (inst != hipSuccess) {
+        (void)hipGetLastError();
+        return HH_ERR_LAUNCH;
+    }
+    if (g_graphs.size() >= kMaxGraphs) {
+        size_t lru = 0;
+        for (size_t i = 1; i < g_graphs.size(); ++i)
+            if (g_graphs[i].last_use < g_graphs[lru].last_use) lru = i;
+        (void)hipGraphExecDestroy(g_graphs[lru].exec);
+        g_graphs.erase(g_graphs.begin() + lru);
+    }
+    g_graphs.push_back(GraphEntry{a, st, tun, ws->mem, ws->cap_msgs, exec, ++g_graph_clock});
+    return hipGraphLaunch(exec, st) == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+}
+
+template <int W>
+hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, const DeviceInfo& di,
+                            const hh_tuning& tun) {
+    const LaunchShape ls = launch_shape(a, di, tun);
+    EventPair* ev = timing_begin(st);
+    // the null stream cannot be captured; timed calls launch directly
+    if (tun.use_graph && st != nullptr && !ev) return launch_graph<W>(a, st, ws, ls, tun);
+    enqueue_sequence<W>(a, st, ws, ls, tun, ev);
+    return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
 }
 
 }  // namespace
@@ -423,6 +531,11 @@ hh_status timing_collect(uint32_t* launches, double* total_ms) {
 }
 
 void release_bucketed() {
+    {
+        std::lock_guard<std::mutex> lock(g_graph_mutex);
+        for (auto& e : g_graphs) (void)hipGraphExecDestroy(e.exec);
+        g_graphs.clear();
+    }
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     for (auto& w : g_ws) {
         if (w.mem) {
