@@ -105,6 +105,15 @@ hh_status hh_hash64_uniform(const uint64_t* keys, uint32_t n_keys, const uint32_
                             const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
                             uint64_t length, uint64_t n_msgs, uint64_t* out, void* stream);
 
+/* Counter-mode keyed PRF (the random-number use case of Sec. 1): message j
+ * (j < n) is the 8-byte little-endian encoding of c = counter_base + j
+ * (mod 2^64), hashed under key c mod n_keys; out[w*j ..] receives its
+ * width_words-word hash.  Identical to hh_hash* over those messages, but no
+ * input buffer or offsets/lengths exist: each thread builds its message in
+ * registers. */
+hh_status hh_prf(uint32_t width_words, const uint64_t* keys, uint32_t n_keys,
+                 uint64_t counter_base, uint64_t n, uint64_t* out, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Incremental hashing (Sec. 4.5: only size mod 32 enters the hash, so a stream
  * is fully described by the 1024-bit state once whole packets are consumed).

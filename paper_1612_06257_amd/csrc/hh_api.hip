@@ -133,6 +133,16 @@ hh_status hh_hash64_uniform(const uint64_t* keys, uint32_t n_keys, const uint32_
     return hh::launch_thread(a, length, (hipStream_t)stream);
 }
 
+hh_status hh_prf(uint32_t width_words, const uint64_t* keys, uint32_t n_keys,
+                 uint64_t counter_base, uint64_t n, uint64_t* out, void* stream) {
+    if (n == 0) return HH_OK;
+    if (!keys || n_keys == 0 || !out) return HH_ERR_INVALID_ARG;
+    if (width_words != 1 && width_words != 2 && width_words != 4) return HH_ERR_INVALID_ARG;
+    hh_status s = hh::check_device(nullptr);
+    if (s != HH_OK) return s;
+    return hh::launch_prf(width_words, keys, n_keys, counter_base, n, out, (hipStream_t)stream);
+}
+
 hh_status hh_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
                         uint64_t* states, uint64_t n, void* stream) {
     if (n == 0) return HH_OK;

@@ -48,6 +48,32 @@ __global__ __launch_bounds__(256) void hh_quad_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Counter-mode keyed PRF: message j is the 8-byte little-endian encoding of
+// c = counter_base + j (mod 2^64), hashed under key c mod n_keys.  An 8-byte
+// message has no whole packet; its remainder packet (Sec. 4.5, r = 8) is the
+// counter in lane 0 and zeros, so nothing is read but the key.
+
+template <int W>
+__global__ __launch_bounds__(256) void hh_prf_kernel(const u64* __restrict__ keys, u32 n_keys,
+                                                     u64 counter_base, u64 n,
+                                                     u64* __restrict__ out) {
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    for (u64 j = (u64)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const u64 c = counter_base + j;
+        const u64* kp = keys + 4 * (c % n_keys);
+        const u64 key[4] = {kp[0], kp[1], kp[2], kp[3]};
+        State4 s;
+        reset4(s, key);
+        const u64 pk[4] = {c, 0, 0, 0};
+        remainder4(s, 8u, pk);
+        u64 sum[4];
+        finalize4(s, sum);
+#pragma unroll
+        for (int i = 0; i < W; ++i) out[(u64)W * j + i] = sum[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // incremental hashing: states[16*s + 4*v + q] = lane q of vector v
 // (v0, v1, mul0, mul1).
 
@@ -151,6 +177,21 @@ hh_status launch_quad(const HashArgs& a, hipStream_t st) {
         default: hipLaunchKernelGGL(hh_quad_kernel<4>, dim3(grid), dim3(block), 0, st, a.keys,
                                     a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets,
                                     a.lengths, a.n, a.out); break;
+    }
+    return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+}
+
+hh_status launch_prf(u32 width, const u64* keys, u32 n_keys, u64 counter_base, u64 n, u64* out,
+                     hipStream_t st) {
+    const unsigned block = 256;
+    const unsigned grid = grid_for(n, block);
+    switch (width) {
+        case 1: hipLaunchKernelGGL(hh_prf_kernel<1>, dim3(grid), dim3(block), 0, st, keys, n_keys,
+                                   counter_base, n, out); break;
+        case 2: hipLaunchKernelGGL(hh_prf_kernel<2>, dim3(grid), dim3(block), 0, st, keys, n_keys,
+                                   counter_base, n, out); break;
+        default: hipLaunchKernelGGL(hh_prf_kernel<4>, dim3(grid), dim3(block), 0, st, keys,
+                                    n_keys, counter_base, n, out); break;
     }
     return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
 }

@@ -67,6 +67,8 @@ def lib() -> ctypes.CDLL:
         L.hh_hash_path.restype = ctypes.c_int
         L.hh_hash64_uniform.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp]
         L.hh_hash64_uniform.restype = ctypes.c_int
+        L.hh_prf.argtypes = [_u32, _vp, _u32, _u64, _u64, _vp, _vp]
+        L.hh_prf.restype = ctypes.c_int
         L.hh_state_init.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp]
         L.hh_state_init.restype = ctypes.c_int
         L.hh_state_update.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp]
@@ -181,6 +183,26 @@ def hash64_uniform(keys, data, offsets, length: int, key_idx=None, out=None) -> 
     _check(lib().hh_hash64_uniform(_ptr(keys), keys.shape[0], _ptr(key_idx), _ptr(data),
                                    data.numel(), _ptr(offsets), int(length), n, _ptr(out),
                                    _stream()))
+    return out
+
+
+def prf(keys: torch.Tensor, n: int, counter_base: int = 0, width: int = 1,
+        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Counter-mode PRF: row j is the hash of the 8-byte little-endian counter
+    counter_base + j under key (counter_base + j) mod n_keys."""
+    _dev(keys, "keys", _W64, 2)
+    if keys.shape[1] != 4 or keys.shape[0] < 1:
+        raise ValueError("keys must have shape (n_keys >= 1, 4)")
+    if width not in (1, 2, 4):
+        raise ValueError("width must be 1, 2 or 4 words")
+    if out is None:
+        out = torch.empty((n, width), dtype=torch.int64, device=keys.device)
+    else:
+        _dev(out, "out", _W64, 2)
+        if tuple(out.shape) != (n, width):
+            raise ValueError("out must have shape (n, width)")
+    _check(lib().hh_prf(width, _ptr(keys), keys.shape[0], int(counter_base) % (1 << 64), n,
+                        _ptr(out), _stream()))
     return out
 
 
