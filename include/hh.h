@@ -147,6 +147,25 @@ hh_status hh_state_final(uint64_t* states, const uint32_t* state_idx, const uint
                          uint64_t n, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Avalanche statistics (the strengthened avalanche test of Sec. 6.1 and the
+ * finalization-round study of Sec. 4.3).  For every sample s < n_samples it
+ * hashes (64-bit, `rounds` finalization rounds, 1..4; the hash proper uses 4)
+ * a message of msg_bytes (1..32) bytes and the same message with input bit
+ * b flipped, for b in [bit_first, bit_first + bit_count) (bit_count <= 32,
+ * bit_first + bit_count <= 8*msg_bytes; bit b is bit b%8 of byte b/8), and
+ * adds to counts[64*(b - bit_first) + k] (device, uint64, caller-zeroed) the
+ * number of samples whose output bit k changed.
+ *   mode 0: key word w (0..3) and message word w (4..7, little-endian, bytes
+ *           beyond msg_bytes cleared) of sample s are output 8s+w+1 of
+ *           SplitMix64 (Steele, Lea, Flood 2014) seeded with `seed`;
+ *   mode 1: the message is the little-endian encoding of s (bytes beyond
+ *           msg_bytes cleared) under the one key `key` (host, 4 words): with
+ *           n_samples = 2^(8*msg_bytes) every input is enumerated. */
+hh_status hh_avalanche(int mode, uint32_t msg_bytes, uint32_t rounds, uint64_t seed,
+                       const uint64_t key[4], uint64_t n_samples, uint32_t bit_first,
+                       uint32_t bit_count, uint64_t* counts, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Tuning of the bucketed path (host-side settings, process-wide). */
 typedef struct {
     uint32_t lane4_min_bytes;   /* messages at least this long go to the persistent

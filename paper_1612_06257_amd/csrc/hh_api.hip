@@ -176,6 +176,20 @@ hh_status hh_state_final(uint64_t* states, const uint32_t* state_idx, const uint
                                  width_words, out, out_offsets, n, (hipStream_t)stream);
 }
 
+hh_status hh_avalanche(int mode, uint32_t msg_bytes, uint32_t rounds, uint64_t seed,
+                       const uint64_t key[4], uint64_t n_samples, uint32_t bit_first,
+                       uint32_t bit_count, uint64_t* counts, void* stream) {
+    if (n_samples == 0) return HH_OK;
+    if ((mode != 0 && mode != 1) || msg_bytes < 1 || msg_bytes > 32 || rounds < 1 ||
+        rounds > 4 || bit_count < 1 || bit_count > 32 || !counts ||
+        (uint64_t)bit_first + bit_count > 8ull * msg_bytes || (mode == 1 && !key))
+        return HH_ERR_INVALID_ARG;
+    hh_status s = hh::check_device(nullptr);
+    if (s != HH_OK) return s;
+    return hh::launch_avalanche(mode, msg_bytes, rounds, seed, key, n_samples, bit_first,
+                                bit_count, counts, (hipStream_t)stream);
+}
+
 void hh_get_tuning(hh_tuning* t) {
     if (t) *t = hh::current_tuning();
 }

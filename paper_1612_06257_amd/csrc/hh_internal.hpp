@@ -33,6 +33,10 @@ hh_status launch_state_step(bool final_step, uint64_t* states, const uint32_t* s
                             const uint64_t* lengths, const uint8_t* width_words, uint64_t* out,
                             const uint64_t* out_offsets, uint64_t n, hipStream_t st);
 
+hh_status launch_avalanche(int mode, uint32_t msg_bytes, uint32_t rounds, uint64_t seed,
+                           const uint64_t key[4], uint64_t n, uint32_t bit_first,
+                           uint32_t bit_count, uint64_t* counts, hipStream_t st);
+
 // current device is a gfx950 (cached per device); HH_OK or an error status
 hh_status check_device(int* device_out);
 

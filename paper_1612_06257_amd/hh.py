@@ -69,6 +69,9 @@ def lib() -> ctypes.CDLL:
         L.hh_hash64_uniform.restype = ctypes.c_int
         L.hh_prf.argtypes = [_u32, _vp, _u32, _u64, _u64, _vp, _vp]
         L.hh_prf.restype = ctypes.c_int
+        L.hh_avalanche.argtypes = [ctypes.c_int, _u32, _u32, _u64, _vp, _u64, _u32, _u32, _vp,
+                                   _vp]
+        L.hh_avalanche.restype = ctypes.c_int
         L.hh_state_init.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp]
         L.hh_state_init.restype = ctypes.c_int
         L.hh_state_update.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp]
@@ -204,6 +207,33 @@ def prf(keys: torch.Tensor, n: int, counter_base: int = 0, width: int = 1,
     _check(lib().hh_prf(width, _ptr(keys), keys.shape[0], int(counter_base) % (1 << 64), n,
                         _ptr(out), _stream()))
     return out
+
+
+def avalanche_counts(msg_bytes: int, n_samples: int, rounds: int = 4, seed: int = 0,
+                     key=None, bits=None) -> torch.Tensor:
+    """Flip counts of output bits (64 columns) per flipped input bit (rows),
+    int64 tensor on the GPU.  key=None: SplitMix64 keys and messages from
+    `seed`; else the messages enumerate little-endian sample indices under
+    that key (4 words)."""
+    bits = range(8 * msg_bytes) if bits is None else bits
+    bits = list(bits)
+    counts = torch.zeros((len(bits), 64), dtype=torch.int64, device="cuda")
+    kbuf = None
+    if key is not None:
+        kbuf = (ctypes.c_uint64 * 4)(*[int(x) % (1 << 64) for x in key])
+    mode = 0 if key is None else 1
+    i = 0
+    while i < len(bits):
+        first = bits[i]
+        cnt = 1
+        while cnt < 32 and i + cnt < len(bits) and bits[i + cnt] == first + cnt:
+            cnt += 1
+        view = counts[i:i + cnt]
+        _check(lib().hh_avalanche(mode, msg_bytes, rounds, int(seed) % (1 << 64),
+                                  None if kbuf is None else ctypes.cast(kbuf, _vp), n_samples,
+                                  first, cnt, _ptr(view), _stream()))
+        i += cnt
+    return counts
 
 
 def state_init(keys, n: int, key_idx=None, states=None) -> torch.Tensor:

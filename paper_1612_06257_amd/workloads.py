@@ -194,3 +194,34 @@ def serving_trace(n_requests: int, rate_per_s: float, s: float = 1.1, lo: int = 
     offsets = _packed_offsets(lengths)
     data = _random_bytes(rng, int(lengths.sum())) if materialize else np.zeros(0, np.uint8)
     return Trace(seed, rate_per_s, arrival, keys, key_idx, width, data, offsets, lengths)
+
+
+# --- SplitMix64 inputs for the avalanche studies ----------------------------
+# SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+# generators", OOPSLA 2014): the state advances by the golden gamma
+# 0x9e3779b97f4a7c15 and each output is mix(state).  Output number i (i >= 1)
+# of the generator seeded with `seed` is mix(seed + i * gamma).
+
+_SM_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_SM_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_SM_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64_outputs(seed: int, index: np.ndarray) -> np.ndarray:
+    """Outputs number `index` (uint64 array, >= 1) of SplitMix64(seed)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed % 2**64) + np.asarray(index, np.uint64) * _SM_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _SM_M1
+        z = (z ^ (z >> np.uint64(27))) * _SM_M2
+        return z ^ (z >> np.uint64(31))
+
+
+def avalanche_inputs(seed: int, n: int, msg_bytes: int):
+    """Keys (n, 4) and messages (n, msg_bytes) of the SplitMix64 avalanche
+    stream: key word w of sample s is output 8s+w+1, message word w output
+    8s+4+w+1 (little-endian bytes, cut to msg_bytes)."""
+    s = np.arange(n, dtype=np.uint64)[:, None]
+    keys = splitmix64_outputs(seed, 8 * s + np.arange(4, dtype=np.uint64) + 1)
+    words = splitmix64_outputs(seed, 8 * s + 4 + np.arange(4, dtype=np.uint64) + 1)
+    msgs = words.astype("<u8").view(np.uint8).reshape(n, 32)[:, :msg_bytes].copy()
+    return keys, msgs
