@@ -122,29 +122,57 @@ hh_status hh_prf(uint32_t width_words, const uint64_t* keys, uint32_t n_keys,
  */
 #define HH_STATE_WORDS 16
 
-/* states[16*s ..] = Reset(keys[key_idx[s]]) for s < n (key_idx NULL: key 0). */
+/* The state array holds n_states states (16*n_states words).  An item whose
+ * state index is n_states or more is skipped: it reads and writes nothing.
+ *
+ * For k < n: states[16*t ..] = Reset(keys[key_idx[k]]) (Sec. 4.4), where
+ * t = state_idx[k] (state_idx NULL: t = k; key_idx NULL: key 0; key indices
+ * are clamped to n_keys - 1). */
 hh_status hh_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
-                        uint64_t* states, uint64_t n, void* stream);
+                        uint64_t* states, uint64_t n_states, const uint32_t* state_idx, uint64_t n,
+                        void* stream);
 
 /* Item k folds the whole packets of data[offsets[k] .. + lengths[k]) into
  * state state_idx[k] (state_idx NULL: state k) and stores the state back.
  * lengths[k] should be a multiple of 32; only its whole packets are consumed
  * (lengths[k] rounded down to a multiple of 32).  Two items must not name the
- * same state in one call. */
-hh_status hh_state_update(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
-                          uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
-                          uint64_t n, void* stream);
+ * same state in one call.  Byte ranges are clamped to data_bytes. */
+hh_status hh_state_update(uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
+                          const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                          const uint64_t* lengths, uint64_t n, void* stream);
 
 /* Item k takes state state_idx[k], folds in its bytes (any length: whole
  * packets, then the remainder step with r = lengths[k] mod 32, which is the
  * stream's total size mod 32 because earlier updates were whole packets),
- * finalizes and writes width_words[k] (1, 2 or 4; NULL = 1) words to
- * out[out_offsets[k] ..] (out_offsets NULL: out[4*k ..]).  The stored state
- * is not modified, so a stream can be finished more than once. */
-hh_status hh_state_final(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
-                         uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
-                         const uint8_t* width_words, uint64_t* out, const uint64_t* out_offsets,
-                         uint64_t n, void* stream);
+ * finalizes (Sec. 4.3) and writes width_words[k] (1, 2 or 4; NULL = 1) words
+ * to out[out_offsets[k] ..] (out_offsets NULL: out[4*k ..]); words at index
+ * out_words or beyond are not written.  The stored state is not modified,
+ * so a stream can be finished more than once. */
+hh_status hh_state_final(uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
+                         const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                         const uint64_t* lengths, const uint8_t* width_words, uint64_t* out,
+                         uint64_t out_words, const uint64_t* out_offsets, uint64_t n,
+                         void* stream);
+
+/* One launch of mixed items (a serving iteration): item k with
+ * width_words[k] == 0 is an update exactly as in hh_state_update; any other
+ * width finishes as in hh_state_final.  width_words is required; out may be
+ * NULL when no item finishes (out_words is then taken as 0). */
+hh_status hh_state_step(uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
+                        const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                        const uint64_t* lengths, const uint8_t* width_words, uint64_t* out,
+                        uint64_t out_words, const uint64_t* out_offsets, uint64_t n,
+                        void* stream);
+
+/* Device byte copies for request ingress (the serving loop moves many
+ * payloads into its arena with one launch): for k < n,
+ * dst[dst_offs[k] .. + lens[k]) = src[src_offs[k] .. + lens[k]), each
+ * segment clamped to both buffers.  Segments must not overlap each other in
+ * dst or overlap src.  max_len (the longest lens[k]) only sizes the launch:
+ * any value gives the same bytes. */
+hh_status hh_copy_segments(uint8_t* dst, uint64_t dst_bytes, const uint8_t* src,
+                           uint64_t src_bytes, const uint64_t* src_offs, const uint64_t* dst_offs,
+                           const uint64_t* lens, uint64_t n, uint64_t max_len, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Avalanche statistics (the strengthened avalanche test of Sec. 6.1 and the

@@ -144,36 +144,66 @@ hh_status hh_prf(uint32_t width_words, const uint64_t* keys, uint32_t n_keys,
 }
 
 hh_status hh_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
-                        uint64_t* states, uint64_t n, void* stream) {
+                        uint64_t* states, uint64_t n_states, const uint32_t* state_idx, uint64_t n,
+                        void* stream) {
     if (n == 0) return HH_OK;
     if (!keys || n_keys == 0 || !states) return HH_ERR_INVALID_ARG;
     hh_status s = hh::check_device(nullptr);
     if (s != HH_OK) return s;
-    return hh::launch_state_init(keys, n_keys, key_idx, states, n, (hipStream_t)stream);
+    return hh::launch_state_init(keys, n_keys, key_idx, states, n_states, state_idx, n,
+                                 (hipStream_t)stream);
 }
 
-hh_status hh_state_update(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
-                          uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
-                          uint64_t n, void* stream) {
+hh_status hh_copy_segments(uint8_t* dst, uint64_t dst_bytes, const uint8_t* src,
+                           uint64_t src_bytes, const uint64_t* src_offs, const uint64_t* dst_offs,
+                           const uint64_t* lens, uint64_t n, uint64_t max_len, void* stream) {
+    if (n == 0) return HH_OK;
+    if (!dst || !src || !src_offs || !dst_offs || !lens) return HH_ERR_INVALID_ARG;
+    hh_status s = hh::check_device(nullptr);
+    if (s != HH_OK) return s;
+    return hh::launch_copy_segments(dst, dst_bytes, src, src_bytes, src_offs, dst_offs, lens, n,
+                                    max_len, (hipStream_t)stream);
+}
+
+hh_status hh_state_update(uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
+                          const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                          const uint64_t* lengths, uint64_t n, void* stream) {
     if (n == 0) return HH_OK;
     if (!states || !offsets || !lengths || (!data && data_bytes != 0)) return HH_ERR_INVALID_ARG;
     hh_status s = hh::check_device(nullptr);
     if (s != HH_OK) return s;
-    return hh::launch_state_step(false, states, state_idx, data, data_bytes, offsets, lengths,
-                                 nullptr, nullptr, nullptr, n, (hipStream_t)stream);
+    return hh::launch_state_step(0, states, n_states, state_idx, data, data_bytes, offsets,
+                                 lengths, nullptr, nullptr, 0, nullptr, n, (hipStream_t)stream);
 }
 
-hh_status hh_state_final(uint64_t* states, const uint32_t* state_idx, const uint8_t* data,
-                         uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
-                         const uint8_t* width_words, uint64_t* out, const uint64_t* out_offsets,
-                         uint64_t n, void* stream) {
+hh_status hh_state_final(uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
+                         const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                         const uint64_t* lengths, const uint8_t* width_words, uint64_t* out,
+                         uint64_t out_words, const uint64_t* out_offsets, uint64_t n,
+                         void* stream) {
     if (n == 0) return HH_OK;
     if (!states || !offsets || !lengths || !out || (!data && data_bytes != 0))
         return HH_ERR_INVALID_ARG;
     hh_status s = hh::check_device(nullptr);
     if (s != HH_OK) return s;
-    return hh::launch_state_step(true, states, state_idx, data, data_bytes, offsets, lengths,
-                                 width_words, out, out_offsets, n, (hipStream_t)stream);
+    return hh::launch_state_step(1, states, n_states, state_idx, data, data_bytes, offsets,
+                                 lengths, width_words, out, out_words, out_offsets, n,
+                                 (hipStream_t)stream);
+}
+
+hh_status hh_state_step(uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
+                        const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
+                        const uint64_t* lengths, const uint8_t* width_words, uint64_t* out,
+                        uint64_t out_words, const uint64_t* out_offsets, uint64_t n,
+                        void* stream) {
+    if (n == 0) return HH_OK;
+    if (!states || !offsets || !lengths || !width_words || (!data && data_bytes != 0))
+        return HH_ERR_INVALID_ARG;
+    hh_status s = hh::check_device(nullptr);
+    if (s != HH_OK) return s;
+    return hh::launch_state_step(2, states, n_states, state_idx, data, data_bytes, offsets,
+                                 lengths, width_words, out, out ? out_words : 0, out_offsets, n,
+                                 (hipStream_t)stream);
 }
 
 hh_status hh_avalanche(int mode, uint32_t msg_bytes, uint32_t rounds, uint64_t seed,

@@ -27,10 +27,16 @@ hh_status launch_bucketed(const HashArgs& a, hipStream_t st);
 hh_status launch_prf(uint32_t width, const uint64_t* keys, uint32_t n_keys, uint64_t counter_base,
                      uint64_t n, uint64_t* out, hipStream_t st);
 hh_status launch_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
-                            uint64_t* states, uint64_t n, hipStream_t st);
-hh_status launch_state_step(bool final_step, uint64_t* states, const uint32_t* state_idx,
-                            const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
-                            const uint64_t* lengths, const uint8_t* width_words, uint64_t* out,
+                            uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
+                            uint64_t n, hipStream_t st);
+hh_status launch_copy_segments(uint8_t* dst, uint64_t dst_bytes, const uint8_t* src,
+                               uint64_t src_bytes, const uint64_t* src_offs,
+                               const uint64_t* dst_offs, const uint64_t* lens, uint64_t n,
+                               uint64_t max_len, hipStream_t st);
+hh_status launch_state_step(int mode, uint64_t* states, uint64_t n_states,
+                            const uint32_t* state_idx, const uint8_t* data, uint64_t data_bytes,
+                            const uint64_t* offsets, const uint64_t* lengths,
+                            const uint8_t* width_words, uint64_t* out, uint64_t out_words,
                             const uint64_t* out_offsets, uint64_t n, hipStream_t st);
 
 hh_status launch_avalanche(int mode, uint32_t msg_bytes, uint32_t rounds, uint64_t seed,

@@ -72,12 +72,16 @@ def lib() -> ctypes.CDLL:
         L.hh_avalanche.argtypes = [ctypes.c_int, _u32, _u32, _u64, _vp, _u64, _u32, _u32, _vp,
                                    _vp]
         L.hh_avalanche.restype = ctypes.c_int
-        L.hh_state_init.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp]
+        L.hh_copy_segments.argtypes = [_vp, _u64, _vp, _u64, _vp, _vp, _vp, _u64, _u64, _vp]
+        L.hh_copy_segments.restype = ctypes.c_int
+        L.hh_state_init.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp, _u64, _vp]
         L.hh_state_init.restype = ctypes.c_int
-        L.hh_state_update.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp, _u64, _vp]
+        L.hh_state_update.argtypes = [_vp, _u64, _vp, _vp, _u64, _vp, _vp, _u64, _vp]
         L.hh_state_update.restype = ctypes.c_int
-        L.hh_state_final.argtypes = [_vp, _vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _u64, _vp]
+        L.hh_state_final.argtypes = [_vp, _u64, _vp, _vp, _u64, _vp, _vp, _vp, _vp, _u64, _vp, _u64, _vp]
         L.hh_state_final.restype = ctypes.c_int
+        L.hh_state_step.argtypes = L.hh_state_final.argtypes
+        L.hh_state_step.restype = ctypes.c_int
         L.hh_get_tuning.argtypes = [ctypes.POINTER(_Tuning)]
         L.hh_get_tuning.restype = None
         L.hh_set_tuning.argtypes = [ctypes.POINTER(_Tuning)]
@@ -236,22 +240,44 @@ def avalanche_counts(msg_bytes: int, n_samples: int, rounds: int = 4, seed: int 
     return counts
 
 
-def state_init(keys, n: int, key_idx=None, states=None) -> torch.Tensor:
-    """(n, 16) device states after Reset (Sec. 4.4)."""
+def state_init(keys, n: int, key_idx=None, states=None, state_idx=None) -> torch.Tensor:
+    """Reset (Sec. 4.4) n states: state state_idx[k] (k if None) from key
+    key_idx[k] (0 if None).  Returns the (rows, 16) state tensor."""
     _dev(keys, "keys", _W64, 2)
     if key_idx is not None:
         _dev(key_idx, "key_idx", _W32, 1)
         if key_idx.numel() != n:
             raise ValueError("key_idx must have n entries")
+    if state_idx is not None:
+        _dev(state_idx, "state_idx", _W32, 1)
+        if state_idx.numel() != n:
+            raise ValueError("state_idx must have n entries")
+        if states is None:
+            raise ValueError("states is required with state_idx")
     if states is None:
         states = torch.empty((n, STATE_WORDS), dtype=torch.int64, device=keys.device)
     else:
         _dev(states, "states", _W64, 2)
-        if states.shape[0] < n or states.shape[1] != STATE_WORDS:
+        if states.shape[1] != STATE_WORDS or (state_idx is None and states.shape[0] < n):
             raise ValueError("states must have shape (>= n, 16)")
-    _check(lib().hh_state_init(_ptr(keys), keys.shape[0], _ptr(key_idx), _ptr(states), n,
-                               _stream()))
+    _check(lib().hh_state_init(_ptr(keys), keys.shape[0], _ptr(key_idx), _ptr(states),
+                               states.shape[0], _ptr(state_idx), n, _stream()))
     return states
+
+
+def copy_segments(dst: torch.Tensor, src: torch.Tensor, src_offs: torch.Tensor,
+                  dst_offs: torch.Tensor, lens: torch.Tensor, max_len: int = 1 << 16) -> None:
+    """dst[dst_offs[k]:+lens[k]] = src[src_offs[k]:+lens[k]] for every k, one
+    launch.  max_len (the longest segment) only sizes the launch."""
+    _dev(dst, "dst", (torch.uint8,), 1)
+    _dev(src, "src", (torch.uint8,), 1)
+    for t, nm in ((src_offs, "src_offs"), (dst_offs, "dst_offs"), (lens, "lens")):
+        _dev(t, nm, _W64, 1)
+    n = lens.numel()
+    if src_offs.numel() != n or dst_offs.numel() != n:
+        raise ValueError("segment arrays differ in size")
+    _check(lib().hh_copy_segments(_ptr(dst), dst.numel(), _ptr(src), src.numel(), _ptr(src_offs),
+                                  _ptr(dst_offs), _ptr(lens), n, max_len, _stream()))
 
 
 def state_update(states, data, offsets, lengths, state_idx=None) -> None:
@@ -261,12 +287,14 @@ def state_update(states, data, offsets, lengths, state_idx=None) -> None:
     _dev(offsets, "offsets", _W64, 1)
     _dev(lengths, "lengths", _W64, 1)
     n = offsets.numel()
+    if lengths.numel() != n:
+        raise ValueError("offsets and lengths differ in size")
     if state_idx is not None:
         _dev(state_idx, "state_idx", _W32, 1)
         if state_idx.numel() != n:
             raise ValueError("state_idx must have one entry per item")
-    _check(lib().hh_state_update(_ptr(states), _ptr(state_idx), _ptr(data), data.numel(),
-                                 _ptr(offsets), _ptr(lengths), n, _stream()))
+    _check(lib().hh_state_update(_ptr(states), states.shape[0], _ptr(state_idx), _ptr(data),
+                                 data.numel(), _ptr(offsets), _ptr(lengths), n, _stream()))
 
 
 def state_final(states, data, offsets, lengths, width_words=None, out=None, out_offsets=None,
@@ -278,20 +306,54 @@ def state_final(states, data, offsets, lengths, width_words=None, out=None, out_
     _dev(offsets, "offsets", _W64, 1)
     _dev(lengths, "lengths", _W64, 1)
     n = offsets.numel()
-    if width_words is not None:
-        _dev(width_words, "width_words", (torch.uint8,), 1)
-    if state_idx is not None:
-        _dev(state_idx, "state_idx", _W32, 1)
-    if out_offsets is not None:
-        _dev(out_offsets, "out_offsets", _W64, 1)
-        if out is None:
-            raise ValueError("out is required with out_offsets")
+    if lengths.numel() != n:
+        raise ValueError("offsets and lengths differ in size")
+    for t, nm, dt in ((width_words, "width_words", (torch.uint8,)), (state_idx, "state_idx", _W32),
+                      (out_offsets, "out_offsets", _W64)):
+        if t is not None:
+            _dev(t, nm, dt, 1)
+            if t.numel() != n:
+                raise ValueError("%s must have one entry per item" % nm)
+    if out_offsets is not None and out is None:
+        raise ValueError("out is required with out_offsets")
     if out is None:
         out = torch.zeros((n, 4), dtype=torch.int64, device=offsets.device)
-    _check(lib().hh_state_final(_ptr(states), _ptr(state_idx), _ptr(data), data.numel(),
-                                _ptr(offsets), _ptr(lengths), _ptr(width_words), _ptr(out),
-                                _ptr(out_offsets), n, _stream()))
+    else:
+        if out.dtype not in _W64 or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous 64-bit device tensor")
+        if out_offsets is None and out.numel() < 4 * n:
+            raise ValueError("out must hold 4 words per item")
+    _check(lib().hh_state_final(_ptr(states), states.shape[0], _ptr(state_idx), _ptr(data),
+                                data.numel(), _ptr(offsets), _ptr(lengths), _ptr(width_words),
+                                _ptr(out), out.numel(), _ptr(out_offsets), n, _stream()))
     return out
+
+
+def state_step(states, data, offsets, lengths, width_words, out=None, out_offsets=None,
+               state_idx=None) -> None:
+    """Mixed items in one launch: width_words[k] == 0 folds whole packets into
+    the state (as state_update), any other width finishes (as state_final)."""
+    _dev(states, "states", _W64, 2)
+    _dev(data, "data", (torch.uint8,), 1)
+    _dev(offsets, "offsets", _W64, 1)
+    _dev(lengths, "lengths", _W64, 1)
+    n = offsets.numel()
+    if lengths.numel() != n:
+        raise ValueError("offsets and lengths differ in size")
+    for t, nm, dt in ((width_words, "width_words", (torch.uint8,)), (state_idx, "state_idx", _W32),
+                      (out_offsets, "out_offsets", _W64)):
+        if t is not None:
+            _dev(t, nm, dt, 1)
+            if t.numel() != n:
+                raise ValueError("%s must have one entry per item" % nm)
+    if width_words is None:
+        raise ValueError("width_words is required")
+    if out is not None and (out.dtype not in _W64 or not out.is_cuda or not out.is_contiguous()):
+        raise ValueError("out must be a contiguous 64-bit device tensor")
+    _check(lib().hh_state_step(_ptr(states), states.shape[0], _ptr(state_idx), _ptr(data),
+                               data.numel(), _ptr(offsets), _ptr(lengths), _ptr(width_words),
+                               _ptr(out), 0 if out is None else out.numel(), _ptr(out_offsets), n,
+                               _stream()))
 
 
 def constants():

@@ -100,11 +100,14 @@ class GpuBackend:
     """Device side of the loop: payload arena, states, outputs, launches.
 
     source="device": the trace's payloads sit in a device ingress buffer and
-    admission copies them into the arena (device to device);
+    admission moves all of an iteration's payloads into the arena with one
+    segment-copy launch on the compute stream;
     source="host": they sit in pinned host memory and admission copies them
-    host to device.  Copies run on their own stream; the compute stream waits
-    for them with an event.  Per-iteration item lists go through a ring of
-    pinned staging buffers so that no copy waits for the host."""
+    host to device on a copy stream that the compute stream waits for.
+    Admission resets the new states in place.  Per-iteration item lists go
+    through a ring of pinned staging buffers so that no copy waits for the
+    host, and finished hashes are written compacted in launch order so that
+    one contiguous copy brings them back."""
 
     RING = 6  # staging sets; more than the scheduler's run-ahead + 1
 
@@ -130,49 +133,62 @@ class GpuBackend:
             self.ingress.copy_(src)
         self.copy_stream = torch.cuda.Stream()
         self.compute_stream = torch.cuda.current_stream()
-        # item metadata layout per staging set (bytes): 2 x (offs u64, lens u64,
-        # out_offs u64, slots u32, widths u8) for updates and finals
-        self.meta_bytes = 2 * max_slots * (8 + 8 + 8 + 4 + 1) + 128
+        # item metadata per staging set: offs u64, lens u64, out offs u64,
+        # slots u32, widths u8 for at most max_slots items, each array 8-aligned
+        self.meta_bytes = max_slots * (8 + 8 + 8 + 4 + 1) + 64
         self.h_meta = [torch.empty(self.meta_bytes, dtype=torch.uint8, pin_memory=True)
                        for _ in range(self.RING)]
         self.d_meta = [torch.empty(self.meta_bytes, dtype=torch.uint8, device="cuda")
                        for _ in range(self.RING)]
         self.h_res = [torch.empty((max_slots, 4), dtype=torch.int64, pin_memory=True)
                       for _ in range(self.RING)]
-        self.h_adm = [torch.empty(2 * max_slots * 4, dtype=torch.uint8, pin_memory=True)
+        # admission metadata per staging set: src offs u64, arena offs u64,
+        # lens u64, key index u32, slot u32
+        self.adm_bytes = max_slots * 32
+        self.h_adm = [torch.empty(self.adm_bytes, dtype=torch.uint8, pin_memory=True)
                       for _ in range(self.RING)]
-        self.d_adm = [torch.empty(2 * max_slots * 4, dtype=torch.uint8, device="cuda")
+        self.d_adm = [torch.empty(self.adm_bytes, dtype=torch.uint8, device="cuda")
                       for _ in range(self.RING)]
-        self.fresh = torch.zeros((max_slots, hh.STATE_WORDS), dtype=torch.int64, device="cuda")
         self.k = 0
         self.ka = 0
 
     def admit(self, reqs: List[Request]) -> None:
         """Copy the payloads of newly admitted requests into the arena and
-        reset their states."""
+        reset their states in place."""
         torch = self.torch
         if not reqs:
             return
-        with torch.cuda.stream(self.copy_stream):
-            for r in reqs:
-                if r.length:
-                    self.arena[r.arena_off:r.arena_off + r.length].copy_(
-                        self.ingress[r.src:r.src + r.length], non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(self.copy_stream)
-        self.compute_stream.wait_event(ev)
         n = len(reqs)
         i = self.ka % self.RING
         self.ka += 1
         h = self.h_adm[i].numpy()
-        h[:4 * n].view(np.int32)[:] = [r.key_idx for r in reqs]
-        h[4 * n:8 * n].view(np.int32)[:] = [r.slot for r in reqs]
+        src = np.fromiter((r.src for r in reqs), np.int64, n)
+        dst = np.fromiter((r.arena_off for r in reqs), np.int64, n)
+        lens = np.fromiter((r.length for r in reqs), np.int64, n)
+        h[:8 * n].view(np.int64)[:] = src
+        h[8 * n:16 * n].view(np.int64)[:] = dst
+        h[16 * n:24 * n].view(np.int64)[:] = lens
+        h[24 * n:28 * n].view(np.int32)[:] = np.fromiter((r.key_idx for r in reqs), np.int32, n)
+        h[28 * n:32 * n].view(np.int32)[:] = np.fromiter((r.slot for r in reqs), np.int32, n)
         d = self.d_adm[i]
-        d[:8 * n].copy_(self.h_adm[i][:8 * n], non_blocking=True)
-        kidx = d[:4 * n].view(torch.int32)
-        slots = d[4 * n:8 * n].view(torch.int32)
-        fresh = self.hh.state_init(self.keys, n, kidx, self.fresh)
-        self.states.index_copy_(0, slots.long(), fresh[:n])
+        d[:32 * n].copy_(self.h_adm[i][:32 * n], non_blocking=True)
+        if self.source == "device":
+            # one launch moves every payload, in stream order before the
+            # iteration's updates
+            self.hh.copy_segments(self.arena, self.ingress, d[:8 * n].view(torch.int64),
+                                  d[8 * n:16 * n].view(torch.int64),
+                                  d[16 * n:24 * n].view(torch.int64), int(lens.max()))
+        else:
+            with torch.cuda.stream(self.copy_stream):
+                for r in reqs:
+                    if r.length:
+                        self.arena[r.arena_off:r.arena_off + r.length].copy_(
+                            self.ingress[r.src:r.src + r.length], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(self.copy_stream)
+            self.compute_stream.wait_event(ev)
+        self.hh.state_init(self.keys, n, d[24 * n:28 * n].view(torch.int32), self.states,
+                           d[28 * n:32 * n].view(torch.int32))
 
     @staticmethod
     def _put(h: np.ndarray, off: int, arr: np.ndarray, dt) -> Tuple[int, int]:
@@ -183,40 +199,47 @@ class GpuBackend:
 
     def launch(self, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens, fin_widths):
         """One iteration: fold whole-packet chunks into the states of
-        upd_slots, finish fin_slots.  Arrays of equal length per group.
-        Returns a ticket for done()/wait()/results()."""
+        upd_slots, finish fin_slots, all in one kernel launch.  Arrays of
+        equal length per group.  Returns a ticket for done()/wait()/results()."""
         torch, hh = self.torch, self.hh
         i = self.k % self.RING
         self.k += 1
-        h = self.h_meta[i].numpy()
-        regs = {}
-        off = 0
-        for name, arr, dt in (("uo", upd_offs, np.int64), ("ul", upd_lens, np.int64),
-                              ("us", upd_slots, np.int32), ("fo", fin_offs, np.int64),
-                              ("fl", fin_lens, np.int64), ("foo", 4 * np.asarray(fin_slots, np.int64), np.int64),
-                              ("fs", fin_slots, np.int32), ("fw", fin_widths, np.uint8)):
-            off = (off + 7) // 8 * 8
-            regs[name] = self._put(h, off, arr, dt)
-            off += regs[name][1]
-        d = self.d_meta[i]
-        d[:off].copy_(self.h_meta[i][:off], non_blocking=True)
-
-        def view(name, dt):
-            o, nb = regs[name]
-            return d[o:o + nb].view(dt)
-
         n_upd, n_fin = len(upd_slots), len(fin_slots)
-        if n_upd:
-            hh.state_update(self.states, self.arena, view("uo", torch.int64),
-                            view("ul", torch.int64), view("us", torch.int32))
+        n = n_upd + n_fin
         res = None
-        if n_fin:
-            slots = view("fs", torch.int32)
-            hh.state_final(self.states, self.arena, view("fo", torch.int64),
-                           view("fl", torch.int64), view("fw", torch.uint8),
-                           self.out.view(-1), view("foo", torch.int64), slots)
-            res = self.h_res[i][:n_fin]
-            res.copy_(self.out.index_select(0, slots.long()), non_blocking=True)
+        if n:
+            h = self.h_meta[i].numpy()
+            # updates first, then finals; a final's words go to out[4 * j]
+            # for its rank j among the finals
+            out_offs = np.zeros(n, np.int64)
+            out_offs[n_upd:] = 4 * np.arange(n_fin, dtype=np.int64)
+            widths = np.zeros(n, np.uint8)
+            widths[n_upd:] = fin_widths
+            regs = {}
+            off = 0
+            for name, parts, dt in (("o", (upd_offs, fin_offs), np.int64),
+                                    ("l", (upd_lens, fin_lens), np.int64),
+                                    ("oo", (out_offs,), np.int64),
+                                    ("s", (upd_slots, fin_slots), np.int32),
+                                    ("w", (widths,), np.uint8)):
+                arr = np.concatenate([np.asarray(a, dt) for a in parts])
+                off = (off + 7) // 8 * 8
+                regs[name] = self._put(h, off, arr, dt)
+                off += regs[name][1]
+            d = self.d_meta[i]
+            d[:off].copy_(self.h_meta[i][:off], non_blocking=True)
+
+            def view(name, dt):
+                o, nb = regs[name]
+                return d[o:o + nb].view(dt)
+
+            hh.state_step(self.states, self.arena, view("o", torch.int64), view("l", torch.int64),
+                          view("w", torch.uint8), self.out.view(-1), view("oo", torch.int64),
+                          view("s", torch.int32))
+            if n_fin:
+                # results land compacted in launch order: one contiguous copy out
+                res = self.h_res[i][:n_fin]
+                res.copy_(self.out[:n_fin], non_blocking=True)
         ev = torch.cuda.Event()
         ev.record(self.compute_stream)
         return (ev, res)

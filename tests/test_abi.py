@@ -59,11 +59,16 @@ def test_invalid_arguments_rejected_without_device():
     assert L.hh_hash64(dummy, 1, None, None, 8, dummy, dummy, 3, dummy, None) == 1
     assert L.hh_hash_path(0, 3, dummy, 1, None, dummy, 8, dummy, dummy, 3, dummy, None) == 1
     assert L.hh_hash_path(9, 1, dummy, 1, None, dummy, 8, dummy, dummy, 3, dummy, None) in (1, 2)
-    assert L.hh_state_update(None, None, dummy, 8, dummy, dummy, 2, None) == 1
-    assert L.hh_state_final(dummy, None, dummy, 8, dummy, dummy, None, None, None, 2, None) == 1
+    assert L.hh_state_update(None, 4, None, dummy, 8, dummy, dummy, 2, None) == 1
+    assert L.hh_state_final(dummy, 4, None, dummy, 8, dummy, dummy, None, None, 8, None, 2,
+                            None) == 1
     # n == 0 is a no-op that succeeds even with NULL pointers
     assert L.hh_hash64(None, 0, None, None, 0, None, None, 0, None, None) == 0
-    assert L.hh_state_init(None, 0, None, None, 0, None) == 0
+    assert L.hh_state_init(None, 0, None, None, 0, None, 0, None) == 0
+    assert L.hh_state_init(None, 1, None, dummy, 4, None, 1, None) == 1
+    assert L.hh_copy_segments(None, 0, None, 0, None, None, None, 0, 0, None) == 0
+    assert L.hh_copy_segments(None, 8, dummy, 8, dummy, dummy, dummy, 1, 8, None) == 1
+    assert L.hh_copy_segments(dummy, 8, dummy, 8, dummy, None, dummy, 1, 8, None) == 1
 
 
 def test_no_device_reported_as_unsupported():

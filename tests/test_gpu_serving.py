@@ -43,3 +43,113 @@ def test_serving_results_match_alone_and_oracle(hh, source):
     one = hh.to_u64(hh.hash(keys, data, offs, lens, kidx, 4))
     for i, r in enumerate(sample):
         assert tuple(int(x) for x in one[i][:r.width]) == r.result
+
+
+def test_copy_segments_matches_slices(hh):
+    announce("copy_segments")
+    rng = np.random.default_rng(5)
+    src = rng.integers(0, 256, 1 << 20, dtype=np.uint8)
+    n = 700
+    lens = rng.integers(0, 9000, n)
+    lens[::50] = 0
+    lens[1::50] = 7                               # shorter than one word
+    soff = rng.integers(0, src.size - 9000, n)
+    # disjoint destinations at odd offsets, one segment running past the end
+    dst_size = int(lens.sum()) + 3 * n + 100
+    doff = np.cumsum(np.concatenate([[1], lens[:-1] + 3]))
+    doff_last = dst_size - 5
+    doff[-1] = doff_last
+    lens[-1] = 40                                  # clamped to the 5 bytes left
+    want = np.zeros(dst_size, np.uint8)
+    for s, d_, L in zip(soff, doff, lens):
+        L = min(L, dst_size - d_)
+        want[d_:d_ + L] = src[s:s + L]
+    dst = torch.zeros(dst_size, dtype=torch.uint8, device="cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int64)).cuda()
+    s_dev = torch.from_numpy(src).cuda()
+    # the launch-shape hint changes nothing but speed
+    for hint in (0, 9000, 1 << 30):
+        dst.zero_()
+        hh.copy_segments(dst, s_dev, t(soff), t(doff), t(lens), hint)
+        assert np.array_equal(dst.cpu().numpy(), want), hint
+
+
+def test_state_init_into_slots(hh):
+    announce("state_init slots")
+    rng = np.random.default_rng(6)
+    keys = torch.from_numpy(rng.integers(0, 2**64, (5, 4), dtype=np.uint64)).view(
+        torch.int64).cuda()
+    n = 90
+    kidx = torch.from_numpy(rng.integers(0, 5, n).astype(np.int32)).cuda()
+    slots = torch.from_numpy(rng.permutation(200)[:n].astype(np.int32)).cuda()
+    dense = hh.state_init(keys, n, kidx)
+    states = torch.full((200, hh.STATE_WORDS), 7, dtype=torch.int64, device="cuda")
+    hh.state_init(keys, n, kidx, states, slots)
+    torch.cuda.synchronize()
+    assert torch.equal(states[slots.long()], dense)
+    untouched = torch.ones(200, dtype=torch.bool, device="cuda")
+    untouched[slots.long()] = False
+    assert bool((states[untouched] == 7).all())
+
+
+def test_state_indices_past_the_array_are_skipped(hh):
+    announce("state bounds")
+    rng = np.random.default_rng(12)
+    keys = torch.from_numpy(rng.integers(0, 2**64, (2, 4), dtype=np.uint64)).view(
+        torch.int64).cuda()
+    data = torch.from_numpy(rng.integers(0, 256, 4096, dtype=np.uint8)).cuda()
+    states = torch.full((8, hh.STATE_WORDS), 3, dtype=torch.int64, device="cuda")
+    slots = torch.tensor([0, 8, 5, 1 << 30], dtype=torch.int32, device="cuda")
+    hh.state_init(keys, 4, None, states, slots)
+    offs = torch.tensor([0, 64, 128, 192], dtype=torch.int64, device="cuda")
+    lens = torch.full((4,), 64, dtype=torch.int64, device="cuda")
+    hh.state_update(states, data, offs, lens, slots)
+    # out holds 6 words: item 0 (offset 0) fits, item 2 (offset 4) is cut to 2 words
+    out = torch.full((6,), -1, dtype=torch.int64, device="cuda")
+    oo = torch.tensor([0, 0, 4, 0], dtype=torch.int64, device="cuda")
+    ww = torch.full((4,), 4, dtype=torch.uint8, device="cuda")
+    hh.state_final(states, data, offs + 64, lens - 1, ww, out, oo, slots)
+    torch.cuda.synchronize()
+    rest = [i for i in range(8) if i not in (0, 5)]
+    assert bool((states[rest] == 3).all())
+    key = keys.cpu().numpy().view(np.uint64)[0]
+    d = data.cpu().numpy()
+    h0 = oracle.hash_words(key, d[0:64].tobytes() + d[64:127].tobytes(), 4)
+    h2 = oracle.hash_words(key, d[128:192].tobytes() + d[192:255].tobytes(), 4)
+    got = hh.to_u64(out).tolist()
+    assert got[:4] == [int(x) for x in h0]
+    assert got[4:6] == [int(x) for x in h2[:2]]
+
+
+def test_state_step_mixed_equals_separate_calls(hh):
+    announce("state_step mixed")
+    rng = np.random.default_rng(13)
+    keys = torch.from_numpy(rng.integers(0, 2**64, (3, 4), dtype=np.uint64)).view(
+        torch.int64).cuda()
+    data = torch.from_numpy(rng.integers(0, 256, 1 << 16, dtype=np.uint8)).cuda()
+    n = 300
+    kidx = torch.from_numpy(rng.integers(0, 3, n).astype(np.int32)).cuda()
+    offs = torch.from_numpy(rng.integers(0, 60000, n).astype(np.int64)).cuda()
+    widths = np.array([0, 1, 2, 4], np.uint8)[rng.integers(0, 4, n)]
+    lens_np = rng.integers(0, 3000, n).astype(np.int64)
+    lens_np[widths == 0] &= ~31                      # updates take whole packets
+    lens = torch.from_numpy(lens_np).cuda()
+    ww = torch.from_numpy(widths).cuda()
+    a = hh.state_init(keys, n, kidx)
+    b = a.clone()
+    out_a = torch.full((n, 4), -1, dtype=torch.int64, device="cuda")
+    out_b = out_a.clone()
+    hh.state_step(a, data, offs, lens, ww, out_a.view(-1))
+    upd = torch.from_numpy(np.flatnonzero(widths == 0).astype(np.int32)).cuda()
+    fin = torch.from_numpy(np.flatnonzero(widths != 0).astype(np.int32)).cuda()
+    hh.state_update(b, data, offs[upd.long()], lens[upd.long()], upd)
+    hh.state_final(b, data, offs[fin.long()], lens[fin.long()], ww[fin.long()], out_b.view(-1),
+                   4 * fin.long(), fin)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(out_a, out_b)
+    # an update-only call needs no output buffer
+    hh.state_step(a, data, offs[upd.long()], lens[upd.long()], ww[upd.long()], None, None, upd)
+    hh.state_update(b, data, offs[upd.long()], lens[upd.long()], upd)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
