@@ -195,8 +195,7 @@ def main(argv=None) -> int:
         tuned = autotune.tune(k, d, o, L, ki, 1, cache_path=None)
         path = tuned["path"]
         if path == "bucketed":
-            hh.set_tuning(**dict(hh.get_tuning(), **{x: tuned[x] for x in (
-                "long_ring", "waves_per_cu", "lane4_min_bytes", "use_graph")}))
+            hh.set_tuning(**dict(hh.get_tuning(), **{x: tuned[x] for x in autotune.TUNING_KEYS}))
         print("[bench] autotuned: %s" % json.dumps(tuned), file=sys.stderr, flush=True)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):

@@ -203,6 +203,11 @@ typedef struct {
     uint32_t use_graph;         /* capture planner + hash launches in a hipGraph */
     uint32_t long_ring;         /* packets in flight per thread in the persistent
                                    kernel: 24, 32, 48 or 64 */
+    uint32_t isolate_long;      /* 1: the items that set the critical path (first
+                                   message within 2x of the longest, at most a
+                                   quarter of the CUs' worth) run on CUs whose
+                                   other waves take no short dynamic items;
+                                   0: off.  Only with waves_per_cu <= 4. */
 } hh_tuning;
 
 void hh_get_tuning(hh_tuning* t);

@@ -31,6 +31,8 @@ RINGS = (24, 32, 48)
 WAVES_PER_CU = (4, 8)
 THRESHOLDS = (64, 128, 512)
 GRAPH = (0, 1)
+ISOLATE = (1, 0)
+TUNING_KEYS = ("long_ring", "waves_per_cu", "lane4_min_bytes", "use_graph", "isolate_long")
 
 
 def _log2_bucket(x: float) -> int:
@@ -76,9 +78,12 @@ def _time(fn, reps: int) -> float:
 
 
 def candidates():
-    for ring, wpc, thr, g in itertools.product(RINGS, WAVES_PER_CU, THRESHOLDS, GRAPH):
+    for ring, wpc, thr, g, iso in itertools.product(RINGS, WAVES_PER_CU, THRESHOLDS, GRAPH,
+                                                    ISOLATE):
+        if iso and wpc > 4:
+            continue  # isolation needs one workgroup per CU
         yield {"path": "bucketed", "long_ring": ring, "waves_per_cu": wpc,
-               "lane4_min_bytes": thr, "use_graph": g}
+               "lane4_min_bytes": thr, "use_graph": g, "isolate_long": iso}
     yield {"path": "lane1"}
     yield {"path": "lane4"}
 
@@ -104,9 +109,10 @@ def tune(keys, data, offsets, lengths, key_idx=None, width: int = 1, reps: int =
     finally:
         hh.set_tuning(**saved)
     sec, best = min(results, key=lambda r: r[0])
-    default = next(s for s, c in results if c["path"] == "bucketed" and all(
-        c[k] == saved[k] for k in ("long_ring", "waves_per_cu", "lane4_min_bytes", "use_graph")))
-    entry = dict(best, ms=sec * 1e3, default_ms=default * 1e3, candidates=len(results))
+    default = next((s for s, c in results if c["path"] == "bucketed" and all(
+        c[k] == saved[k] for k in TUNING_KEYS)), None)
+    entry = dict(best, ms=sec * 1e3, default_ms=None if default is None else default * 1e3,
+                 candidates=len(results))
     if cache_path:
         cache = _load(cache_path)
         cache[signature(lengths, width)] = entry
@@ -127,6 +133,6 @@ def hash(keys, data, offsets, lengths, key_idx=None, width: int = 1, out=None,
     if entry is None:
         return hh.hash(keys, data, offsets, lengths, key_idx, width, "auto", out)
     if entry["path"] == "bucketed":
-        hh.set_tuning(**dict(hh.get_tuning(), **{k: entry[k] for k in (
-            "long_ring", "waves_per_cu", "lane4_min_bytes", "use_graph")}))
+        hh.set_tuning(**dict(hh.get_tuning(), **{k: entry[k] for k in TUNING_KEYS
+                                                 if k in entry}))
     return hh.hash(keys, data, offsets, lengths, key_idx, width, entry["path"], out)

@@ -17,9 +17,16 @@
 //                          bucket (8 buckets per octave of the packet count)
 //   hh_scatter_kernel      bucket start offsets (longest bucket first, every
 //                          block recomputes the 256-entry prefix), then long
-//                          list -> bucket order
-//   hh_long_kernel<W>      persistent: wave w first takes item w (16 messages,
-//                          4 threads each), then items from an atomic counter
+//                          list -> bucket order; block 0 also decides how many
+//                          leading (critical) items get a CU of their own
+//   hh_long_kernel<W>      persistent: critical item b on wave 0 of workgroup
+//                          b, the other waves of that workgroup idle; every
+//                          other wave takes one item (16 messages, 4 threads
+//                          each), then items from an atomic counter
+// A chain slows down by about 10% when other waves of its CU stream data
+// alongside it (they share the CU's load path), which is why the few chains
+// that set the batch's duration run alone on their CUs when the rest of the
+// batch is light enough for the remaining CUs.
 // Messages inside a bucket come out in any order; each message's result only
 // depends on its own bytes, so outputs are deterministic.
 
@@ -38,7 +45,8 @@ constexpr u64 kPriorityBytes = 64u << 10;  // items this long run at wave priori
 struct Plan {
     u32 n_long;     // messages appended to the long list
     u32 item_next;  // next dynamic item of hh_long_kernel
-    u32 pad[2];
+    u32 n_iso;      // leading items whose workgroups take no dynamic items
+    u32 pad;
     u32 hist[kBuckets];
     u32 cursor[kBuckets];
 };
@@ -52,17 +60,27 @@ __device__ __forceinline__ u32 bucket_of(u32 npk) {
     return lz * 8u + sub;
 }
 
+// smallest packet count of bucket b (inverse of bucket_of, at least 1)
+__device__ __forceinline__ u64 bucket_floor(u32 b) {
+    const u32 lz = b >> 3, sub = b & 7u;
+    const u64 v = lz >= 3u ? (u64)(8u + sub) << (lz - 3u) : (u64)((8u + sub) >> (3u - lz));
+    return v ? v : 1u;
+}
+
+// Isolation pays when the whole batch can stream from HBM in less than half
+// the critical chain: packets * 32 B / 5.5 TB/s <= chain packets * 39 ns / 2,
+// i.e. packets <= chain packets * 3350 (measured copy bandwidth and Update
+// latency on MI355X).
+constexpr u64 kIsoPacketsPerChainPacket = 3350;
+
 __device__ __forceinline__ u32 packets_capped(u64 len) {
     const u64 npk = len >> 5;
     return npk > 0xffffffffull ? 0xffffffffu : (u32)npk;
 }
 
-__global__ __launch_bounds__(256) void hh_plan_reset_kernel(Plan* __restrict__ plan,
-                                                            u32 first_dynamic_item) {
+__global__ __launch_bounds__(256) void hh_plan_reset_kernel(Plan* __restrict__ plan) {
     u32* w = (u32*)plan;
     for (u32 i = threadIdx.x; i < sizeof(Plan) / 4; i += blockDim.x) w[i] = 0u;
-    __syncthreads();
-    if (threadIdx.x == 0) plan->item_next = first_dynamic_item;
 }
 
 template <int W>
@@ -121,17 +139,21 @@ constexpr int kScatterPer = 4;
 __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
     const u64* __restrict__ lengths, Plan* __restrict__ plan, const u32* __restrict__ long_list,
-    u32* __restrict__ order) {
+    u32* __restrict__ order, u32 iso_cap) {
     __shared__ u32 cnt[kBuckets];
     __shared__ u32 base[kBuckets];
     __shared__ u32 start[kBuckets];
+    __shared__ unsigned long long total_packets;
     // bucket starts: exclusive prefix over buckets, longest bucket first
     {
         const u32 t = threadIdx.x;
         const u32 b = kBuckets - 1u - t;
         const u32 c = plan->hist[b];
         cnt[t] = c;
+        if (t == 0u) total_packets = 0ull;
         __syncthreads();
+        if (blockIdx.x == 0 && c)
+            atomicAdd(&total_packets, (unsigned long long)c * bucket_floor(b));
         for (u32 d = 1; d < kBuckets; d <<= 1) {
             const u32 v = t >= d ? cnt[t - d] : 0u;
             __syncthreads();
@@ -139,6 +161,16 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
             __syncthreads();
         }
         start[b] = cnt[t] - c;
+        // critical items: those holding the messages of the top octave of
+        // lengths (8 buckets down from the longest non-empty one), when they
+        // are few enough to give each a CU of its own and the rest of the
+        // batch is light enough to run on the remaining CUs
+        if (blockIdx.x == 0 && cnt[t] != 0u && (t == 0u || cnt[t - 1u] == 0u)) {
+            const u32 top = cnt[t + 7u < kBuckets ? t + 7u : kBuckets - 1u];
+            const u32 items = (top + 15u) >> 4;
+            const bool light = total_packets <= bucket_floor(b) * kIsoPacketsPerChainPacket;
+            plan->n_iso = (items <= iso_cap && light) ? items : 0u;
+        }
         __syncthreads();
     }
     const u32 n_long = plan->n_long;
@@ -171,9 +203,12 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
     }
 }
 
-// Persistent: 16 messages per item, 4 threads per message.  Wave w (numbered
-// so that waves 0..gridDim.x-1 are the first waves of distinct workgroups)
-// takes item w first, then items from plan->item_next.
+// Persistent: 16 messages per item, 4 threads per message.  With n_iso
+// critical items, wave 0 of workgroup b < n_iso takes item b and the other
+// waves of that workgroup (one workgroup per CU) exit, so the critical chain
+// has the CU to itself.  The remaining waves take items n_iso.. first,
+// numbered so that consecutive items land on distinct workgroups, then items
+// from plan->item_next.
 template <int W, int RING>
 __global__ __launch_bounds__(256) void hh_long_kernel(
     const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
@@ -185,8 +220,17 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
     const int q = (int)(lane & 3u);
     const u32 n_long = plan->n_long;
     const u32 n_items = (n_long + 15u) >> 4;
-    u32 item = (threadIdx.x >> 6) * gridDim.x + blockIdx.x;
-    if (item >= n_items && lane == 0 && threadIdx.x == 0) lds_reserve[0] = 0u;
+    const u32 groups = gridDim.x, g = blockIdx.x, w = threadIdx.x >> 6;
+    const u32 n_iso = plan->n_iso;  // at most a quarter of the workgroups
+    u32 item;
+    if (g < n_iso) {
+        if (w != 0u) return;
+        item = g;
+    } else {
+        item = n_iso + w * (groups - n_iso) + (g - n_iso);
+    }
+    const u32 first_dynamic = n_iso + 4u * (groups - n_iso);
+    if (item >= n_items && threadIdx.x == 0) lds_reserve[0] = 0u;
     while (item < n_items) {
         const u32 k = 16u * item + (lane >> 2);
         // items come longest first: the item's first message decides whether
@@ -196,15 +240,18 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
             __builtin_amdgcn_s_setprio(3);
         else
             __builtin_amdgcn_s_setprio(0);
-        if (k < n_long) {
-            const u32 j = order[k];
+        // the quads of a ragged last item repeat the item's first message
+        // (same cache lines) and store nothing: the wave keeps all lanes on
+        {
+            const bool real = k < n_long;
+            const u32 j = order[real ? k : 16u * item];
             const u64 key_q = keys[4 * key_index(key_idx, n_keys, j) + q];
             const Msg m = message(data, data_bytes, offsets[j], lengths[j]);
             const u64 sum = hash_quad<RING>(key_q, m.p, m.len, q);
-            if (q < W) out[(u64)W * j + q] = sum;
+            if (real && q < W) out[(u64)W * j + q] = sum;
         }
         u32 nxt = 0;
-        if (lane == 0) nxt = atomicAdd(&plan->item_next, 1u);
+        if (lane == 0) nxt = first_dynamic + atomicAdd(&plan->item_next, 1u);
         item = __builtin_amdgcn_readfirstlane(nxt);
     }
 }
@@ -332,6 +379,7 @@ struct LaunchShape {
     u32 lds;
     unsigned split_blocks;
     unsigned scatter_blocks;
+    u32 iso_cap;  // most critical items given a CU each (0: isolation off)
 };
 
 LaunchShape launch_shape(const HashArgs& a, const DeviceInfo& di, const hh_tuning& tun) {
@@ -346,6 +394,8 @@ LaunchShape launch_shape(const HashArgs& a, const DeviceInfo& di, const hh_tunin
         if (di.lds_per_block > 0 && ls.lds > (u32)di.lds_per_block) ls.lds = (u32)di.lds_per_block;
         ls.lds &= ~255u;
     }
+    // a workgroup owns its CU only when one fits per CU
+    ls.iso_cap = (tun.isolate_long && blocks_per_cu == 1u) ? ls.long_blocks / 4u : 0u;
     ls.split_blocks = (unsigned)std::min<u64>((a.n + 255) / 256, 8192);
     ls.scatter_blocks =
         (unsigned)std::min<u64>((a.n + kScatterPer * 256 - 1) / (kScatterPer * 256), 1024);
@@ -357,13 +407,13 @@ LaunchShape launch_shape(const HashArgs& a, const DeviceInfo& di, const hh_tunin
 template <int W>
 void enqueue_sequence(const HashArgs& a, hipStream_t st, const Workspace* ws,
                       const LaunchShape& ls, const hh_tuning& tun, EventPair* ev) {
-    hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan,
-                       ls.long_blocks * 4u);
+    hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan);
     hipLaunchKernelGGL(hh_split_kernel<W>, dim3(ls.split_blocks), dim3(256), 0, st, a.keys,
                        a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.n, a.out,
                        (u64)tun.lane4_min_bytes, ws->plan, ws->long_list);
     hipLaunchKernelGGL(hh_scatter_kernel, dim3(ls.scatter_blocks), dim3(kBuckets), 0, st, a.data,
-                       a.data_bytes, a.offsets, a.lengths, ws->plan, ws->long_list, ws->order);
+                       a.data_bytes, a.offsets, a.lengths, ws->plan, ws->long_list, ws->order,
+                       ls.iso_cap);
     if (ev && hipEventRecord(ev->start, st) != hipSuccess) (void)hipGetLastError();
 #define HH_LONG(RING)                                                                        \
     hipLaunchKernelGGL((hh_long_kernel<W, RING>), dim3(ls.long_blocks), dim3(256), ls.lds, st, \
@@ -405,7 +455,7 @@ bool same_call(const GraphEntry& e, const HashArgs& a, hipStream_t st, const hh_
            e.a.data_bytes == a.data_bytes && e.a.offsets == a.offsets &&
            e.a.lengths == a.lengths && e.a.n == a.n && e.a.out == a.out && e.a.width == a.width &&
            e.tun.lane4_min_bytes == t.lane4_min_bytes && e.tun.waves_per_cu == t.waves_per_cu &&
-           e.tun.long_ring == t.long_ring;
+           e.tun.long_ring == t.long_ring && e.tun.isolate_long == t.isolate_long;
 }
 
 void drop_graphs_of(const u8* ws_mem) {

@@ -38,12 +38,19 @@ __global__ __launch_bounds__(256) void hh_quad_kernel(
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
     const u64* __restrict__ lengths, u64 n, u64* __restrict__ out) {
     const int q = threadIdx.x & 3;
-    const u64 stride = ((u64)gridDim.x * blockDim.x) >> 2;
-    for (u64 j = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 2; j < n; j += stride) {
+    const u64 quad = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const u64 stride = ((u64)gridDim.x * blockDim.x) >> 2;  // a multiple of 16
+    // wave-uniform loop: quads past n repeat the wave's first message and
+    // store nothing, so the wave keeps every lane on (a partly masked wave
+    // runs the chain about 10% slower)
+    for (u64 base = quad & ~15ull; base < n; base += stride) {
+        const u64 k = base + (quad & 15u);
+        const bool real = k < n;
+        const u64 j = real ? k : base;
         const u64 key_q = keys[4 * key_index(key_idx, n_keys, j) + q];
         const Msg m = message(data, data_bytes, offsets[j], lengths[j]);
         const u64 sum = hash_quad<kQuadRing>(key_q, m.p, m.len, q);
-        if (q < W) out[(u64)W * j + q] = sum;
+        if (real && q < W) out[(u64)W * j + q] = sum;
     }
 }
 
@@ -143,8 +150,14 @@ __global__ __launch_bounds__(256) void hh_state_step_kernel(
     const u64* __restrict__ lengths, const u8* __restrict__ width_words, u64* __restrict__ out,
     u64 out_words, const u64* __restrict__ out_offsets, u64 n) {
     const int q = threadIdx.x & 3;
-    const u64 stride = ((u64)gridDim.x * blockDim.x) >> 2;
-    for (u64 k = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 2; k < n; k += stride) {
+    const u64 quad = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const u64 stride = ((u64)gridDim.x * blockDim.x) >> 2;  // a multiple of 16
+    // wave-uniform loop: quads past n repeat the wave's first item without
+    // storing anything (it reads what that item's quad reads, in the same
+    // instructions, before any store), so the wave keeps every lane on
+    for (u64 base = quad & ~15ull; base < n; base += stride) {
+        const bool real = base + (quad & 15u) < n;
+        const u64 k = real ? base + (quad & 15u) : base;
         const u64 t = state_idx ? (u64)state_idx[k] : k;
         if (t >= n_states) continue;  // whole quad agrees; the DPP exchange stays in step
         u64* st = states + 16 * t;
@@ -157,12 +170,12 @@ __global__ __launch_bounds__(256) void hh_state_step_kernel(
         load_state1(s, st, q);
         absorb_quad_all<kStateRing>(s, m.p, m.len >> 5, q);
         if (!fin) {
-            store_state1(s, st, q);
+            if (real) store_state1(s, st, q);
         } else {
             if (r) remainder1(s, r, tail);
             const u64 sum = finalize1(s);
             const u64 o = out_offsets ? out_offsets[k] : 4 * k;
-            if ((u32)q < w && o < out_words && (u64)q < out_words - o) out[o + q] = sum;
+            if (real && (u32)q < w && o < out_words && (u64)q < out_words - o) out[o + q] = sum;
         }
     }
 }

@@ -37,7 +37,8 @@ class HHError(RuntimeError):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("lane4_min_bytes", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
-                ("use_graph", ctypes.c_uint32), ("long_ring", ctypes.c_uint32)]
+                ("use_graph", ctypes.c_uint32), ("long_ring", ctypes.c_uint32),
+                ("isolate_long", ctypes.c_uint32)]
 
 
 _lib = None

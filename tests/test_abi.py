@@ -95,4 +95,7 @@ def test_tuning_roundtrip():
     assert hh.get_tuning() == t
     with pytest.raises(hh.HHError):
         hh.set_tuning(waves_per_cu=0)
+    with pytest.raises(hh.HHError):
+        hh.set_tuning(**dict(t, isolate_long=2))
     hh.set_tuning(**t)
+    assert hh.get_tuning() == t

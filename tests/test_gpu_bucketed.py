@@ -35,7 +35,8 @@ def _batch(seed=31, n=2500):
 @pytest.mark.parametrize("tuning", [
     dict(long_ring=24), dict(long_ring=48), dict(long_ring=64), dict(waves_per_cu=8),
     dict(waves_per_cu=12, long_ring=32), dict(lane4_min_bytes=0), dict(lane4_min_bytes=1),
-    dict(lane4_min_bytes=4096), dict(lane4_min_bytes=1 << 30)])
+    dict(lane4_min_bytes=4096), dict(lane4_min_bytes=1 << 30), dict(isolate_long=0),
+    dict(isolate_long=1, waves_per_cu=2), dict(isolate_long=1, waves_per_cu=8)])
 def test_tuning_variants_bit_exact(hh, tuning):
     base = hh.get_tuning()
     keys, key_idx, data, offsets, lengths = _batch()
@@ -47,6 +48,44 @@ def test_tuning_variants_bit_exact(hh, tuning):
         got = hh.to_u64(hh.hash(k, d, o, L, ki, 2, "auto"))
         torch.cuda.synchronize()
         assert_same(got, want, str(tuning))
+    finally:
+        hh.set_tuning(**base)
+
+
+def _isolation_batch(n_top, top_lo, top_hi, n_rest, rest_hi, seed):
+    rng = np.random.default_rng(seed)
+    lens = np.concatenate([rng.integers(top_lo, top_hi, n_top),
+                           rng.integers(0, rest_hi, n_rest)]).astype(np.uint64)
+    rng.shuffle(lens)
+    offsets = (np.cumsum(lens) - lens).astype(np.uint64) + rng.integers(0, 3, lens.size).astype(
+        np.uint64)
+    data = np.frombuffer(rng.bytes(int(offsets[-1] + lens[-1]) + 8), np.uint8).copy()
+    keys = rng.integers(0, 2**64, size=(3, 4), dtype=np.uint64)
+    key_idx = rng.integers(0, 3, lens.size, dtype=np.uint32)
+    return keys, key_idx, data, offsets, lens
+
+
+@pytest.mark.parametrize("case", [
+    # several critical items (top octave spans 4 items of 16)
+    dict(n_top=50, top_lo=200000, top_hi=400000, n_rest=3000, rest_hi=20000, seed=3),
+    # one critical item that is not full
+    dict(n_top=5, top_lo=300000, top_hi=310000, n_rest=500, rest_hi=5000, seed=4),
+    # more top-octave items than a quarter of the CUs: isolation switches off
+    dict(n_top=1500, top_lo=4096, top_hi=8192, n_rest=3000, rest_hi=4096, seed=5),
+    # a batch too heavy for the CUs left over: isolation switches off
+    dict(n_top=20, top_lo=1024, top_hi=1100, n_rest=40000, rest_hi=500, seed=6),
+])
+def test_isolation_regimes_bit_exact(hh, case):
+    announce("isolation", case)
+    keys, key_idx, data, offsets, lengths = _isolation_batch(**case)
+    want = oracle_ref(4, keys, key_idx, data, offsets, lengths)
+    k, ki, d, o, L = batch_to_device(keys, key_idx, data, offsets, lengths)
+    base = hh.get_tuning()
+    try:
+        for iso in (1, 0):
+            hh.set_tuning(**dict(base, isolate_long=iso, waves_per_cu=4))
+            got = hh.to_u64(hh.hash(k, d, o, L, ki, 4, "bucketed"))
+            assert_same(got, want, "isolate_long=%d" % iso)
     finally:
         hh.set_tuning(**base)
 
