@@ -252,9 +252,21 @@ __device__ __forceinline__ u64 load_le64(const u8* p) { return *(const u64_any_a
 // all issued at once, so every load gets half a ring of Updates of latency
 // cover even where the compiler waits for all outstanding loads at the loop
 // head.  All threads of a quad run with the same npk.
+// An empty asm statement that reads v: the compiler has to wait for the load
+// of v before it (one s_waitcnt).  Vector-memory loads retire in issue order,
+// so that wait also covers every load issued before v, and the uses of those
+// values that follow need no wait of their own.  (No instruction, no memory
+// access inside the asm.)
+__device__ __forceinline__ void wait_loaded(u64 v) { asm volatile("" ::"v"(v)); }
+
+// packets per explicit wait in the steady loop (measured on MI355X: 4 beats
+// one wait per packet and one per half-ring on the long-message batch)
+constexpr u32 kWaitGroup = 4;
+
 template <int RING>
 __device__ __forceinline__ void absorb_quad(State1& s, const u8* lp, u32 npk) {
     constexpr u32 H = RING / 2;
+    static_assert(H % kWaitGroup == 0, "the half ring must hold whole wait groups");
     const u32 last = npk - 1u;
     u64 A[H], B[H];
 #pragma unroll
@@ -265,16 +277,30 @@ __device__ __forceinline__ void absorb_quad(State1& s, const u8* lp, u32 npk) {
 #pragma unroll
         for (u32 k = 0; k < H; ++k) B[k] = load_le64(blk + 32u * k);
         // keep the loads here: the scheduler would otherwise sink them
-        // toward their uses and shorten the latency they are given
+        // toward their uses and shorten the latency they are given.  One
+        // wait per kWaitGroup packets instead of one per packet: a wave
+        // issues one instruction per four cycles, so every instruction
+        // saved shortens the chain, while small groups still let the
+        // Updates start as the loads come in.
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (u32 k = 0; k < H; ++k) update1(s, A[k]);
+        for (u32 g0 = 0; g0 < H; g0 += kWaitGroup) {
+            wait_loaded(A[g0 + kWaitGroup - 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (u32 k = g0; k < g0 + kWaitGroup; ++k) update1(s, A[k]);
+        }
         blk += 32u * H;
 #pragma unroll
         for (u32 k = 0; k < H; ++k) A[k] = load_le64(blk + 32u * k);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (u32 k = 0; k < H; ++k) update1(s, B[k]);
+        for (u32 g0 = 0; g0 < H; g0 += kWaitGroup) {
+            wait_loaded(B[g0 + kWaitGroup - 1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (u32 k = g0; k < g0 + kWaitGroup; ++k) update1(s, B[k]);
+        }
     }
     // drain: at most 3H packets remain, A holds the first H of them
 #pragma unroll

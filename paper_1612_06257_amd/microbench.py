@@ -174,6 +174,7 @@ def main(argv=None):
                     r, buf = absorb(L, ring, npk, n_waves, misalign, buf)
                     recs.append(r)
                     print(json.dumps(r), flush=True)
+        _write(args, recs, argv)
         return
     n_up = 20000
     for quad in (True, False):
@@ -184,7 +185,7 @@ def main(argv=None):
         recs.append(chain(L, quad, n_up, 16 * cus, prio_waves=cus))
         print(json.dumps(recs[-1]), flush=True)
     buf = None
-    for ring in (16, 32, 64):
+    for ring in (8, 16, 24, 32, 48, 64):
         r, buf = absorb(L, ring, 32768, 1, 1, buf)
         recs.append(r)
         print(json.dumps(r), flush=True)
@@ -194,6 +195,10 @@ def main(argv=None):
         print(json.dumps(recs[-1]), flush=True)
     recs.append(read_bw(L))
     print(json.dumps(recs[-1]), flush=True)
+    _write(args, recs, argv)
+
+
+def _write(args, recs, argv) -> None:
     if args.json:
         with open(args.json, "w") as f:
             for r in recs:
