@@ -202,7 +202,7 @@ typedef struct {
     uint32_t waves_per_cu;      /* persistent grid: CUs x waves_per_cu waves (4, 8, ...) */
     uint32_t use_graph;         /* capture planner + hash launches in a hipGraph */
     uint32_t long_ring;         /* packets in flight per thread in the persistent
-                                   kernel: 24, 32, 48 or 64 */
+                                   kernel: 36, 48, 72 or 96 */
     uint32_t isolate_long;      /* 1: the items that set the critical path (first
                                    message within 2x of the longest, at most a
                                    quarter of the CUs' worth) run on CUs whose

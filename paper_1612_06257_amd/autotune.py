@@ -27,7 +27,7 @@ from . import hh
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hh_autotune.json")
 
-RINGS = (24, 32, 48)
+RINGS = (48, 72, 96)
 WAVES_PER_CU = (4, 8)
 THRESHOLDS = (64, 128, 512)
 GRAPH = (0, 1)

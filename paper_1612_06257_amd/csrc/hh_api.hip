@@ -14,7 +14,7 @@ namespace {
 std::mutex g_mutex;
 constexpr int kMaxDevices = 64;
 signed char g_device_ok[kMaxDevices];  // 0 unknown, 1 gfx950, -1 other
-hh_tuning g_tuning = {128u, 4u, 0u, 32u, 1u};
+hh_tuning g_tuning = {128u, 4u, 0u, 72u, 1u};
 
 hh_status check_hash_args(const HashArgs& a) {
     if (a.n == 0) return HH_OK;
@@ -228,7 +228,7 @@ hh_status hh_set_tuning(const hh_tuning* t) {
     if (!t || t->waves_per_cu == 0 || t->waves_per_cu > 32 || t->use_graph > 1 ||
         t->isolate_long > 1)
         return HH_ERR_INVALID_ARG;
-    if (t->long_ring != 24 && t->long_ring != 32 && t->long_ring != 48 && t->long_ring != 64)
+    if (t->long_ring != 36 && t->long_ring != 48 && t->long_ring != 72 && t->long_ring != 96)
         return HH_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(hh::g_mutex);
     hh::g_tuning = *t;

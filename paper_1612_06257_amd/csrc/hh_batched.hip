@@ -420,10 +420,10 @@ void enqueue_sequence(const HashArgs& a, hipStream_t st, const Workspace* ws,
                        a.keys, a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, \
                        a.out, ws->plan, ws->order)
     switch (tun.long_ring) {
-        case 24: HH_LONG(24); break;
-        case 32: HH_LONG(32); break;
-        case 64: HH_LONG(64); break;
-        default: HH_LONG(48); break;
+        case 36: HH_LONG(36); break;
+        case 48: HH_LONG(48); break;
+        case 96: HH_LONG(96); break;
+        default: HH_LONG(72); break;
     }
 #undef HH_LONG
     if (ev && hipEventRecord(ev->stop, st) != hipSuccess) (void)hipGetLastError();

@@ -246,12 +246,6 @@ typedef u64 u64_any_align __attribute__((aligned(1)));
 
 __device__ __forceinline__ u64 load_le64(const u8* p) { return *(const u64_any_align*)p; }
 
-// Quad layout: absorb npk (>= 1) whole packets starting at the lane's bytes
-// lp (= message + 8q + 32*first).  The packets in flight form two halves of
-// RING/2: while one half is consumed the other half's loads are in flight,
-// all issued at once, so every load gets half a ring of Updates of latency
-// cover even where the compiler waits for all outstanding loads at the loop
-// head.  All threads of a quad run with the same npk.
 // An empty asm statement that reads v: the compiler has to wait for the load
 // of v before it (one s_waitcnt).  Vector-memory loads retire in issue order,
 // so that wait also covers every load issued before v, and the uses of those
@@ -259,65 +253,85 @@ __device__ __forceinline__ u64 load_le64(const u8* p) { return *(const u64_any_a
 // access inside the asm.)
 __device__ __forceinline__ void wait_loaded(u64 v) { asm volatile("" ::"v"(v)); }
 
-// packets per explicit wait in the steady loop (measured on MI355X: 4 beats
-// one wait per packet and one per half-ring on the long-message batch)
+// packets per explicit wait in the steady loop
 constexpr u32 kWaitGroup = 4;
 
+// One third of the ring in the steady loop: for each group of kWaitGroup
+// packets of X, wait for the group, issue the loads of the same group of Y
+// (consumed two thirds of a ring later), then Update over the group.  The
+// scheduling barriers keep every group's loads and waits where they are
+// written: loads spread one per Update keep the wave's load queue from
+// filling (a burst of them stalls the issue of the rest), and one wait per
+// group instead of one per packet saves instructions (a wave issues one per
+// four cycles, so each one lengthens the chain).
+template <u32 H>
+__device__ __forceinline__ void ring_third(State1& s, u64 (&X)[H], u64 (&Y)[H], const u8* src) {
+#pragma unroll
+    for (u32 g0 = 0; g0 < H; g0 += kWaitGroup) {
+        wait_loaded(X[g0 + kWaitGroup - 1]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (u32 k = g0; k < g0 + kWaitGroup; ++k) Y[k] = load_le64(src + 32u * k);
+#pragma unroll
+        for (u32 k = g0; k < g0 + kWaitGroup; ++k) update1(s, X[k]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Whole packets 0..npk-1 (npk >= 1) at lp + 32*t (this thread's lane: lp
+// already offset by 8*q) through a quad's state.  RING packets are in flight
+// per thread, in three register thirds A, B, C of H = RING/3: while the
+// Updates run over one third, the third consumed after the next one is being
+// loaded, so every load has about two thirds of the ring (2H Updates) to
+// arrive.  All threads of a quad run with the same npk.
 template <int RING>
 __device__ __forceinline__ void absorb_quad(State1& s, const u8* lp, u32 npk) {
-    constexpr u32 H = RING / 2;
-    static_assert(H % kWaitGroup == 0, "the half ring must hold whole wait groups");
+    constexpr u32 H = RING / 3;
+    static_assert(RING % 3 == 0 && H % kWaitGroup == 0, "ring: three thirds of whole groups");
     const u32 last = npk - 1u;
-    u64 A[H], B[H];
+    u64 A[H], B[H], C[H];
+    // one load per barrier: the loop's waits are computed from the order of
+    // the loads in flight, which must be the same here as in the loop
 #pragma unroll
-    for (u32 k = 0; k < H; ++k) A[k] = load_le64(lp + 32u * min(k, last));
-    u32 t0 = 0;
-    for (; t0 + 3u * H < npk; t0 += 2u * H) {
-        const u8* blk = lp + 32u * (t0 + H);
-#pragma unroll
-        for (u32 k = 0; k < H; ++k) B[k] = load_le64(blk + 32u * k);
-        // keep the loads here: the scheduler would otherwise sink them
-        // toward their uses and shorten the latency they are given.  One
-        // wait per kWaitGroup packets instead of one per packet: a wave
-        // issues one instruction per four cycles, so every instruction
-        // saved shortens the chain, while small groups still let the
-        // Updates start as the loads come in.
+    for (u32 k = 0; k < H; ++k) {
+        A[k] = load_le64(lp + 32u * min(k, last));
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (u32 g0 = 0; g0 < H; g0 += kWaitGroup) {
-            wait_loaded(A[g0 + kWaitGroup - 1]);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (u32 k = g0; k < g0 + kWaitGroup; ++k) update1(s, A[k]);
-        }
-        blk += 32u * H;
-#pragma unroll
-        for (u32 k = 0; k < H; ++k) A[k] = load_le64(blk + 32u * k);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (u32 g0 = 0; g0 < H; g0 += kWaitGroup) {
-            wait_loaded(B[g0 + kWaitGroup - 1]);
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (u32 k = g0; k < g0 + kWaitGroup; ++k) update1(s, B[k]);
-        }
     }
-    // drain: at most 3H packets remain, A holds the first H of them
 #pragma unroll
-    for (u32 k = 0; k < H; ++k) B[k] = load_le64(lp + 32u * min(t0 + H + k, last));
-    __builtin_amdgcn_sched_barrier(0);
+    for (u32 k = 0; k < H; ++k) {
+        B[k] = load_le64(lp + 32u * min(H + k, last));
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    u32 t0 = 0;
+    for (; t0 + 5u * H <= npk; t0 += 3u * H) {
+        const u8* nx = lp + 32u * (t0 + 2u * H);
+        ring_third<H>(s, A, C, nx);
+        ring_third<H>(s, B, A, nx + 32u * H);
+        ring_third<H>(s, C, B, nx + 64u * H);
+    }
+    // drain: fewer than 5H packets remain; A and B hold the first 2H of them
+    // (loads past the last packet repeat it and are not used)
 #pragma unroll
-    for (u32 k = 0; k < H; ++k)
+    for (u32 k = 0; k < H; ++k) {
+        C[k] = load_le64(lp + 32u * min(t0 + 2u * H + k, last));
         if (t0 + k < npk) update1(s, A[k]);
+    }
 #pragma unroll
-    for (u32 k = 0; k < H; ++k) A[k] = load_le64(lp + 32u * min(t0 + 2u * H + k, last));
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (u32 k = 0; k < H; ++k)
+    for (u32 k = 0; k < H; ++k) {
+        A[k] = load_le64(lp + 32u * min(t0 + 3u * H + k, last));
         if (t0 + H + k < npk) update1(s, B[k]);
+    }
+#pragma unroll
+    for (u32 k = 0; k < H; ++k) {
+        B[k] = load_le64(lp + 32u * min(t0 + 4u * H + k, last));
+        if (t0 + 2u * H + k < npk) update1(s, C[k]);
+    }
 #pragma unroll
     for (u32 k = 0; k < H; ++k)
-        if (t0 + 2u * H + k < npk) update1(s, A[k]);
+        if (t0 + 3u * H + k < npk) update1(s, A[k]);
+#pragma unroll
+    for (u32 k = 0; k < H; ++k)
+        if (t0 + 4u * H + k < npk) update1(s, B[k]);
 }
 
 // Thread layout: a packet is four unaligned 64-bit loads (two dwordx4).

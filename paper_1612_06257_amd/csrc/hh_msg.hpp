@@ -61,8 +61,8 @@ __device__ __forceinline__ void remainder1(State1& s, u32 r, u64 lane_word) {
 constexpr u64 kMaxPacketsPerCall = 1ull << 31;
 
 constexpr int kThreadRing = 4;  // packets in flight per thread (thread layout)
-constexpr int kQuadRing = 8;    // packets in flight per thread (quad layout, wide grids)
-constexpr int kStateRing = 32;  // packets in flight per thread (streaming-state kernels)
+constexpr int kQuadRing = 12;   // packets in flight per thread (quad layout, wide grids)
+constexpr int kStateRing = 48;  // packets in flight per thread (streaming-state kernels)
 
 // The whole hash of one message in one thread; returns the final lane sums.
 __device__ __forceinline__ void hash_thread(const u64* key, const u8* p, u64 len, u64 sum[4]) {

@@ -138,12 +138,12 @@ int hh_probe_absorb(int ring, const void* data, u64 data_bytes, u64 msg_bytes, u
     hipStream_t st = (hipStream_t)stream;
     const u8* d = (const u8*)data;
     switch (ring) {
-        case 8: hipLaunchKernelGGL(hh_probe_absorb_kernel<8>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
-        case 16: hipLaunchKernelGGL(hh_probe_absorb_kernel<16>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 12: hipLaunchKernelGGL(hh_probe_absorb_kernel<12>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
         case 24: hipLaunchKernelGGL(hh_probe_absorb_kernel<24>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
-        case 32: hipLaunchKernelGGL(hh_probe_absorb_kernel<32>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 36: hipLaunchKernelGGL(hh_probe_absorb_kernel<36>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
         case 48: hipLaunchKernelGGL(hh_probe_absorb_kernel<48>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
-        case 64: hipLaunchKernelGGL(hh_probe_absorb_kernel<64>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 72: hipLaunchKernelGGL(hh_probe_absorb_kernel<72>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
+        case 96: hipLaunchKernelGGL(hh_probe_absorb_kernel<96>, dim3(n_waves), dim3(64), 0, st, d, msg_bytes, misalign, npk, cycles, sink); break;
         default: return 1;
     }
     return hipGetLastError() == hipSuccess ? 0 : 4;

@@ -170,7 +170,7 @@ def main(argv=None):
         buf = None
         for n_waves, npk in ((1, 32768), (4 * cus, 4096)):
             for misalign in (0, 1):
-                for ring in (8, 16, 24, 32, 48, 64):
+                for ring in (12, 24, 36, 48, 72, 96):
                     r, buf = absorb(L, ring, npk, n_waves, misalign, buf)
                     recs.append(r)
                     print(json.dumps(r), flush=True)
@@ -185,7 +185,7 @@ def main(argv=None):
         recs.append(chain(L, quad, n_up, 16 * cus, prio_waves=cus))
         print(json.dumps(recs[-1]), flush=True)
     buf = None
-    for ring in (8, 16, 24, 32, 48, 64):
+    for ring in (12, 24, 36, 48, 72, 96):
         r, buf = absorb(L, ring, 32768, 1, 1, buf)
         recs.append(r)
         print(json.dumps(r), flush=True)

@@ -33,8 +33,8 @@ def _batch(seed=31, n=2500):
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(long_ring=24), dict(long_ring=48), dict(long_ring=64), dict(waves_per_cu=8),
-    dict(waves_per_cu=12, long_ring=32), dict(lane4_min_bytes=0), dict(lane4_min_bytes=1),
+    dict(long_ring=36), dict(long_ring=48), dict(long_ring=96), dict(waves_per_cu=8),
+    dict(waves_per_cu=12, long_ring=48), dict(lane4_min_bytes=0), dict(lane4_min_bytes=1),
     dict(lane4_min_bytes=4096), dict(lane4_min_bytes=1 << 30), dict(isolate_long=0),
     dict(isolate_long=1, waves_per_cu=2), dict(isolate_long=1, waves_per_cu=8)])
 def test_tuning_variants_bit_exact(hh, tuning):

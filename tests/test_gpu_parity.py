@@ -68,12 +68,17 @@ def test_mixed_lengths_and_alignments(hh, path):
 
 @pytest.mark.parametrize("path", PATHS)
 def test_packet_counts_around_prefetch_depths(hh, path):
-    # whole-packet counts 0..80 (covers every ring depth up to 32 and its
-    # steady/drain boundaries) times every start misalignment and tail size
+    # whole-packet counts 0..80 times several tail sizes, then 81..400 (the
+    # loop/drain boundaries of every ring depth up to 96 packets in flight:
+    # the loop runs from 5/3 of a ring and steps by a ring) at every start
+    # misalignment
     rng = np.random.default_rng(3)
     lens = []
     for k in range(0, 81):
         for r in (0, 1, 3, 4, 5, 28, 29, 31):
+            lens.append(32 * k + r)
+    for k in range(81, 401):
+        for r in (0, 5, 31):
             lens.append(32 * k + r)
     msgs = [np.frombuffer(rng.bytes(L), np.uint8) for L in lens]
     data, offsets, lengths = _pack(msgs, rng)
