@@ -29,7 +29,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hh_autotune.jso
 
 RINGS = (48, 72, 96)
 WAVES_PER_CU = (4, 8)
-THRESHOLDS = (64, 128, 512)
+THRESHOLDS = (0, 64, 128, 512)
 GRAPH = (0, 1)
 ISOLATE = (1, 0)
 TUNING_KEYS = ("long_ring", "waves_per_cu", "lane4_min_bytes", "use_graph", "isolate_long")

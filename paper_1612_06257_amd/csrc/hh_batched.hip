@@ -11,7 +11,9 @@
 //
 // Launch sequence on one stream (all device-side, no host synchronisation;
 // optionally captured once per argument set into a hipGraph and replayed):
-//   hh_plan_reset_kernel   zero the plan counters
+//   (hh_plan_reset_kernel  zero the plan: only after a sequence that failed
+//                          part-way; the last wave of hh_long_kernel zeroes
+//                          it otherwise)
 //   hh_split_kernel<W>     L < threshold: hash in-thread;  else: append the
 //                          index to the long list and count it in its length
 //                          bucket (8 buckets per octave of the packet count)
@@ -22,7 +24,8 @@
 //   hh_long_kernel<W>      persistent: critical item b on wave 0 of workgroup
 //                          b, the other waves of that workgroup idle; every
 //                          other wave takes one item (16 messages, 4 threads
-//                          each), then items from an atomic counter
+//                          each), then items from an atomic counter; the last
+//                          wave to finish zeroes the plan
 // A chain slows down by about 10% when other waves of its CU stream data
 // alongside it (they share the CU's load path), which is why the few chains
 // that set the batch's duration run alone on their CUs when the rest of the
@@ -45,8 +48,8 @@ constexpr u64 kPriorityBytes = 64u << 10;  // items this long run at wave priori
 struct Plan {
     u32 n_long;     // messages appended to the long list
     u32 item_next;  // next dynamic item of hh_long_kernel
-    u32 n_iso;      // leading items whose workgroups take no dynamic items
-    u32 pad;
+    u32 n_iso;       // leading items that get a CU each
+    u32 waves_done;  // waves of hh_long_kernel that have retired
     u32 hist[kBuckets];
     u32 cursor[kBuckets];
 };
@@ -83,20 +86,27 @@ __global__ __launch_bounds__(256) void hh_plan_reset_kernel(Plan* __restrict__ p
     for (u32 i = threadIdx.x; i < sizeof(Plan) / 4; i += blockDim.x) w[i] = 0u;
 }
 
+// Split threads per workgroup.  A workgroup reserves its long-list range with
+// one global atomic per pass and flushes its histogram once: device-scope
+// atomics on a few addresses serialise, and one per wave cost several
+// microseconds on a 65,536-message batch.
+constexpr u32 kSplitThreads = 1024;
+constexpr u32 kSplitWaves = kSplitThreads / 64;
+
 template <int W>
-__global__ __launch_bounds__(256) void hh_split_kernel(
+__global__ __launch_bounds__(kSplitThreads) void hh_split_kernel(
     const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
     const u64* __restrict__ lengths, u64 n, u64* __restrict__ out, u64 long_min_bytes,
     Plan* __restrict__ plan, u32* __restrict__ long_list) {
     __shared__ u32 hist[kBuckets];
-    for (u32 i = threadIdx.x; i < kBuckets; i += blockDim.x) hist[i] = 0u;
-    __syncthreads();
-    const u32 lane = threadIdx.x & 63u;
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    // wave-uniform loop so that every lane takes part in the ballot
-    for (u64 base = (u64)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
-        const u64 j = base + lane;
+    __shared__ u32 wave_base[kSplitWaves];
+    for (u32 i = threadIdx.x; i < kBuckets; i += kSplitThreads) hist[i] = 0u;
+    const u32 lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const u64 stride = (u64)gridDim.x * kSplitThreads;
+    // workgroup-uniform loop: every thread reaches the barriers
+    for (u64 base = (u64)blockIdx.x * kSplitThreads; base < n; base += stride) {
+        const u64 j = base + threadIdx.x;
         Msg m{nullptr, 0};
         bool is_long = false;
         if (j < n) {
@@ -104,18 +114,25 @@ __global__ __launch_bounds__(256) void hh_split_kernel(
             is_long = m.len >= long_min_bytes;
         }
         const u64 mask = __ballot(is_long);
-        if (mask) {
-            const u32 count = (u32)__popcll(mask);
-            const u32 leader = (u32)__ffsll((long long)mask) - 1u;
-            u32 slot0 = 0;
-            if (lane == leader) slot0 = atomicAdd(&plan->n_long, count);
-            slot0 = __builtin_amdgcn_readlane(slot0, leader);
-            if (is_long) {
-                const u32 rank = __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
-                long_list[slot0 + rank] = (u32)j;
-                atomicAdd(&hist[bucket_of(packets_capped(m.len))], 1u);
+        __syncthreads();  // the previous pass has read wave_base
+        if (lane == 0) wave_base[wave] = (u32)__popcll(mask);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u32 run = 0;
+            for (u32 w = 0; w < kSplitWaves; ++w) {
+                const u32 c = wave_base[w];
+                wave_base[w] = run;
+                run += c;
             }
+            const u32 first = run ? atomicAdd(&plan->n_long, run) : 0u;
+            for (u32 w = 0; w < kSplitWaves; ++w) wave_base[w] += first;
+        }
+        __syncthreads();
+        if (is_long) {
+            const u32 rank = __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+            long_list[wave_base[wave] + rank] = (u32)j;
+            atomicAdd(&hist[bucket_of(packets_capped(m.len))], 1u);
         }
         if (j < n && !is_long) {
             const u64* kp = keys + 4 * key_index(key_idx, n_keys, j);
@@ -127,7 +144,7 @@ __global__ __launch_bounds__(256) void hh_split_kernel(
         }
     }
     __syncthreads();
-    for (u32 i = threadIdx.x; i < kBuckets; i += blockDim.x)
+    for (u32 i = threadIdx.x; i < kBuckets; i += kSplitThreads)
         if (hist[i]) atomicAdd(&plan->hist[i], hist[i]);
 }
 
@@ -203,6 +220,23 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
     }
 }
 
+// Called by every wave of hh_long_kernel as its last action.  The last wave
+// to retire zeroes the plan for the next call on this workspace (the calls of
+// a workspace are ordered on its stream).  No fence is needed: every plan
+// access of a wave (loads, the item counter's atomic) has returned a value
+// the wave used before it counts itself, and the end of the kernel makes the
+// zeros visible to the next one.  (A device-scope fence here would write back
+// the L2 of the wave's XCD, once per wave.)
+__device__ __forceinline__ void retire_wave(Plan* plan, u32 total_waves, u32 lane) {
+    u32 prev = 0;
+    if (lane == 0) prev = atomicAdd(&plan->waves_done, 1u);
+    prev = __builtin_amdgcn_readfirstlane(prev);
+    if (prev == total_waves - 1u) {
+        u32* w = (u32*)plan;
+        for (u32 i = lane; i < sizeof(Plan) / 4; i += 64u) w[i] = 0u;
+    }
+}
+
 // Persistent: 16 messages per item, 4 threads per message.  With n_iso
 // critical items, wave 0 of workgroup b < n_iso takes item b and the other
 // waves of that workgroup (one workgroup per CU) exit, so the critical chain
@@ -222,9 +256,13 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
     const u32 n_items = (n_long + 15u) >> 4;
     const u32 groups = gridDim.x, g = blockIdx.x, w = threadIdx.x >> 6;
     const u32 n_iso = plan->n_iso;  // at most a quarter of the workgroups
+    const u32 total_waves = groups * 4u;
     u32 item;
     if (g < n_iso) {
-        if (w != 0u) return;
+        if (w != 0u) {
+            retire_wave(plan, total_waves, lane);
+            return;
+        }
         item = g;
     } else {
         item = n_iso + w * (groups - n_iso) + (g - n_iso);
@@ -254,6 +292,7 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
         if (lane == 0) nxt = first_dynamic + atomicAdd(&plan->item_next, 1u);
         item = __builtin_amdgcn_readfirstlane(nxt);
     }
+    retire_wave(plan, total_waves, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -269,6 +308,7 @@ struct Workspace {
     Plan* plan;
     u32* long_list;
     u32* order;
+    bool dirty;  // a sequence failed part-way: zero the plan before the next one
 };
 
 std::mutex g_ws_mutex;
@@ -338,7 +378,7 @@ hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out) {
     for (auto& w : g_ws)
         if (w.device == dev && w.stream == st) ws = &w;
     if (!ws) {
-        g_ws.push_back(Workspace{dev, st, nullptr, 0, nullptr, nullptr, nullptr});
+        g_ws.push_back(Workspace{dev, st, nullptr, 0, nullptr, nullptr, nullptr, false});
         ws = &g_ws.back();
     }
     if (ws->cap_msgs < n || !ws->mem) {
@@ -369,6 +409,7 @@ hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out) {
         ws->plan = (Plan*)mem;
         ws->long_list = (u32*)(mem + plan_bytes);
         ws->order = (u32*)(mem + plan_bytes + list_bytes);
+        ws->dirty = false;
     }
     *out = ws;
     return HH_OK;
@@ -396,19 +437,25 @@ LaunchShape launch_shape(const HashArgs& a, const DeviceInfo& di, const hh_tunin
     }
     // a workgroup owns its CU only when one fits per CU
     ls.iso_cap = (tun.isolate_long && blocks_per_cu == 1u) ? ls.long_blocks / 4u : 0u;
-    ls.split_blocks = (unsigned)std::min<u64>((a.n + 255) / 256, 8192);
+    ls.split_blocks = (unsigned)std::min<u64>((a.n + kSplitThreads - 1) / kSplitThreads, 512);
     ls.scatter_blocks =
         (unsigned)std::min<u64>((a.n + kScatterPer * 256 - 1) / (kScatterPer * 256), 1024);
     return ls;
 }
 
-// The four launches of one bucketed call.  `ev` (may be null) brackets the
+// The launches of one bucketed call: split, scatter, persistent kernel (whose
+// last wave leaves the plan zeroed for the next call; the plan is zeroed
+// when the workspace is allocated, and again by hh_plan_reset_kernel after a
+// sequence that failed part-way).  `ev` (may be null) brackets the
 // persistent kernel for the measurement hook.
 template <int W>
-void enqueue_sequence(const HashArgs& a, hipStream_t st, const Workspace* ws,
-                      const LaunchShape& ls, const hh_tuning& tun, EventPair* ev) {
-    hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan);
-    hipLaunchKernelGGL(hh_split_kernel<W>, dim3(ls.split_blocks), dim3(256), 0, st, a.keys,
+void enqueue_sequence(const HashArgs& a, hipStream_t st, Workspace* ws, const LaunchShape& ls,
+                      const hh_tuning& tun, EventPair* ev) {
+    if (ws->dirty) {
+        hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan);
+        ws->dirty = false;
+    }
+    hipLaunchKernelGGL(hh_split_kernel<W>, dim3(ls.split_blocks), dim3(kSplitThreads), 0, st, a.keys,
                        a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.n, a.out,
                        (u64)tun.lane4_min_bytes, ws->plan, ws->long_list);
     hipLaunchKernelGGL(hh_scatter_kernel, dim3(ls.scatter_blocks), dim3(kBuckets), 0, st, a.data,
@@ -471,7 +518,7 @@ void drop_graphs_of(const u8* ws_mem) {
 }
 
 template <int W>
-hh_status launch_graph(const HashArgs& a, hipStream_t st, const Workspace* ws, const LaunchShape& ls,
+hh_status launch_graph(const HashArgs& a, hipStream_t st, Workspace* ws, const LaunchShape& ls,
                        const hh_tuning& tun) {
     std::lock_guard<std::mutex> lock(g_graph_mutex);
     for (auto& e : g_graphs) {
@@ -516,10 +563,16 @@ hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, co
                             const hh_tuning& tun) {
     const LaunchShape ls = launch_shape(a, di, tun);
     EventPair* ev = timing_begin(st);
+    hh_status s;
     // the null stream cannot be captured; timed calls launch directly
-    if (tun.use_graph && st != nullptr && !ev) return launch_graph<W>(a, st, ws, ls, tun);
-    enqueue_sequence<W>(a, st, ws, ls, tun, ev);
-    return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+    if (tun.use_graph && st != nullptr && !ev) {
+        s = launch_graph<W>(a, st, ws, ls, tun);
+    } else {
+        enqueue_sequence<W>(a, st, ws, ls, tun, ev);
+        s = hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+    }
+    if (s != HH_OK) ws->dirty = true;
+    return s;
 }
 
 }  // namespace

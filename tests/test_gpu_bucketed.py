@@ -139,3 +139,23 @@ def test_autotune_caches_and_stays_bit_exact(hh, tmp_path):
         assert_same(got, want, "autotuned " + str(best))
     finally:
         hh.set_tuning(**base)
+
+
+def test_back_to_back_calls_share_the_plan(hh):
+    # consecutive calls on one stream reuse one workspace; each call's last
+    # wave leaves the plan zeroed for the next one, so batches of different
+    # sizes and mixes queued without any synchronisation must all be exact
+    announce("back-to-back")
+    batches = []
+    for seed, n in ((51, 300), (52, 2500), (53, 200), (54, 1200), (55, 2500)):
+        keys, key_idx, data, offsets, lengths = _batch(seed=seed, n=n)
+        want = oracle_ref(1, keys, key_idx, data, offsets, lengths)
+        batches.append((batch_to_device(keys, key_idx, data, offsets, lengths), want))
+    torch.cuda.synchronize()
+    outs = []
+    for _ in range(3):
+        for (k, ki, d, o, L), _w in batches:
+            outs.append(hh.hash(k, d, o, L, ki, 1, "bucketed"))
+    torch.cuda.synchronize()
+    for i, out in enumerate(outs):
+        assert_same(hh.to_u64(out), batches[i % len(batches)][1], "call %d" % i)
