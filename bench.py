@@ -40,6 +40,15 @@ OUT_BYTES = 8                   # HighwayHash-64 result per message
 KEY_BYTES = 32
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILE_DIR, "hh_long_kernel_lognormal_traffic.json")
+VALU_FILE = os.path.join(PROFILE_DIR, "hh_long_kernel_lognormal_valu.json")
+# integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-op per
+# lane per cycle for a full-rate instruction
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# the paper's own figures (Sec. 5, cycles-per-byte table): HighwayHash AVX2 on
+# one core of a Xeon E5-2690 v3 at 2.6 GHz; context only
+PAPER_CONTEXT = {"cpu": "Xeon E5-2690 v3, one core, 2.6 GHz, AVX2",
+                 "cycles_per_byte": {"8": 7.34, "64": 0.95, "1024": 0.24},
+                 "GBps_at_1024_bytes": round(2.6 / 0.24, 2)}
 CHAIN_FILE = os.path.join(PROFILE_DIR, "microbench_update_chain.json")
 KERNEL_SOURCES = ["paper_1612_06257_amd/csrc/hh_batched.hip", "paper_1612_06257_amd/csrc/hh_msg.hpp",
                   "paper_1612_06257_amd/csrc/hh_device.hpp"]
@@ -246,6 +255,21 @@ def main(argv=None) -> int:
                 "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": traffic,
                 "algorithmic_bytes_per_launch": long_bytes,
                 "kernel_ms_mean": long_ms_mean, "launches_timed": launches}
+    # integer-VALU roof of the same kernel, from its counted VALU instructions
+    # (each a wave of 64 lane-ops) over the mean launch time measured above
+    valu_roof = None
+    vc = load_json(VALU_FILE)
+    if (vc and vc.get("source_sha") == kernel_source_sha() and vc.get("workload") == b.name
+            and long_ms_mean):
+        c = vc["per_launch"]
+        lane_ops = c["SQ_INSTS_VALU"] * 64.0
+        valu_roof = {"bound": "alu", "kernel": "hh_long_kernel",
+                     "achieved": lane_ops / (long_ms_mean * 1e-3) / 1e12,
+                     "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                     "frac": lane_ops / (long_ms_mean * 1e-3) / VALU_PEAK_LANE_OPS,
+                     "valu_insts_per_launch": c["SQ_INSTS_VALU"],
+                     "lds_insts_per_launch": c.get("SQ_INSTS_LDS"),
+                     "lds_bank_conflict_cycles_per_launch": c.get("SQ_LDS_BANK_CONFLICT")}
 
     # critical path: longest message x measured single-wave Update time
     chain = load_json(CHAIN_FILE) or {}
@@ -269,7 +293,9 @@ def main(argv=None) -> int:
         "autotune": tuned,
         "messages_per_s": b.n * args.steps / sec,
         "roofline": roofline,
+        "valu_roofline": valu_roof,
         "critical_path": critical,
+        "paper_context": PAPER_CONTEXT,
     }
 
     if not args.no_plain:

@@ -3,6 +3,7 @@
     python -m paper_1612_06257_amd.profiles_summary stats  <kernel_stats.csv> <out.md> <command>
     python -m paper_1612_06257_amd.profiles_summary traffic <fetch.csv> <write.csv> \
         <copy_fetch.csv> <copy_write.csv> <copy_bytes> <workload> <out.json>
+    python -m paper_1612_06257_amd.profiles_summary valu <sq.csv> <workload> <out.json>
 
 `traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of
 hh_long_kernel by the factor that makes the same counters read the known size
@@ -64,9 +65,38 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
     return rec
 
 
+VALU_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES",
+                 "SQ_WAVE_CYCLES", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_VMEM_RD",
+                 "GRBM_GUI_ACTIVE")
+
+
+def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1"):
+    """Per-dispatch means of the SQ counters of the persistent kernel (one
+    rocprofv3 --pmc run with VALU_COUNTERS), with the kernel-source hash."""
+    sys.path.insert(0, ".")
+    import bench
+    per = {}
+    for r in csv.DictReader(open(path)):
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        if k.startswith(kernel_prefix):
+            per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            kernel = k
+    rec = {"kernel": kernel, "workload": workload, "source_sha": bench.kernel_source_sha(),
+           "per_launch": {c: sum(v) / len(v) for c, v in sorted(per.items())},
+           "launches": len(next(iter(per.values()))),
+           "command": "rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " -d <dir> -o bench "
+                      "--output-format csv -- python -u bench.py --steps 2 --warmup 1 "
+                      "--no-cpu-baseline --no-plain --no-autotune"}
+    json.dump(rec, open(out, "w"), indent=1)
+    open(out, "a").write("\n")
+    return rec
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         kernel_stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "valu":
+        print(json.dumps(valu(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
     else:
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5],
                                  int(sys.argv[6]), sys.argv[7], sys.argv[8]), indent=1))
