@@ -54,8 +54,8 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
         "hbm_bytes_per_launch": f[kernel] * 1024.0 * f_factor + w[kernel] * 1024.0 * w_factor,
         "other_kernels_fetch_kib": {k: v for k, v in f.items() if k != kernel},
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune",
-            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune",
+            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving",
+            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving",
             "rocprofv3 --pmc FETCH_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
             "rocprofv3 --pmc WRITE_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
         ],
@@ -86,7 +86,7 @@ def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1"):
            "launches": len(next(iter(per.values()))),
            "command": "rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " -d <dir> -o bench "
                       "--output-format csv -- python -u bench.py --steps 2 --warmup 1 "
-                      "--no-cpu-baseline --no-plain --no-autotune"}
+                      "--no-cpu-baseline --no-plain --no-autotune --no-serving"}
     json.dump(rec, open(out, "w"), indent=1)
     open(out, "a").write("\n")
     return rec

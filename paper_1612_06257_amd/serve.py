@@ -439,7 +439,12 @@ def load_sweep(n_requests: int = 10000, loads=(0.25, 0.5, 0.8), chunk_bytes: int
 
 
 def bench_summary(n_requests: int = 2000, load: float = 0.5, chunk_bytes: int = 1 << 16) -> dict:
-    """Short run for the benchmark line: saturation plus one Poisson load."""
+    """Short run for the benchmark line: a discarded warm-up pass (first-use
+    allocations, clocks), then saturation plus one Poisson load."""
+    from . import workloads as W
+    warm = W.serving_trace(400, 1.0, seed=W.SEED_BASE + 99)
+    warm.arrival_s[:] = 0.0
+    serve_trace(warm, chunk_bytes=chunk_bytes)
     pts = load_sweep(n_requests, (load,), chunk_bytes)
     return {"saturation": pts[0], "load": pts[1]}
 
