@@ -216,6 +216,13 @@ hh_status hh_set_tuning(const hh_tuning* t);
 /* Free the library's per-device workspaces and cached graphs. */
 hh_status hh_release(void);
 
+/* Device address of pinned host memory (hipHostMalloc'd, e.g. a pinned
+ * torch tensor), for kernels that read item lists from or write results to
+ * host memory directly (the serving loop's long lane).  Returns
+ * HH_ERR_INVALID_ARG for a null pointer and for memory the runtime does not
+ * know as pinned. */
+hh_status hh_pinned_device_pointer(const void* host, void** device);
+
 /* ---------------------------------------------------------------------------
  * Measurement hook (benchmarks, profilers).  While enabled, every call of the
  * bucketed path records a pair of HIP events on its stream around its

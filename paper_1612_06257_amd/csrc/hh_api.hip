@@ -235,6 +235,17 @@ hh_status hh_set_tuning(const hh_tuning* t) {
     return HH_OK;
 }
 
+hh_status hh_pinned_device_pointer(const void* host, void** device) {
+    if (!host || !device) return HH_ERR_INVALID_ARG;
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, const_cast<void*>(host), 0) != hipSuccess || !d) {
+        (void)hipGetLastError();
+        return HH_ERR_INVALID_ARG;
+    }
+    *device = d;
+    return HH_OK;
+}
+
 hh_status hh_release(void) {
     hh::release_bucketed();
     return HH_OK;

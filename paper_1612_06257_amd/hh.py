@@ -74,6 +74,8 @@ def lib() -> ctypes.CDLL:
                                    _vp]
         L.hh_avalanche.restype = ctypes.c_int
         L.hh_copy_segments.argtypes = [_vp, _u64, _vp, _u64, _vp, _vp, _vp, _u64, _u64, _vp]
+        L.hh_pinned_device_pointer.argtypes = [_vp, ctypes.POINTER(_vp)]
+        L.hh_pinned_device_pointer.restype = ctypes.c_int
         L.hh_copy_segments.restype = ctypes.c_int
         L.hh_state_init.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp, _u64, _vp]
         L.hh_state_init.restype = ctypes.c_int
@@ -380,6 +382,31 @@ def set_tuning(**kw) -> None:
 
 def release() -> None:
     _check(lib().hh_release())
+
+
+def pinned_device_pointer(t: torch.Tensor) -> int:
+    """Device address of a pinned host tensor's storage (kernels may read and
+    write it directly)."""
+    if not isinstance(t, torch.Tensor) or t.is_cuda or not t.is_pinned():
+        raise ValueError("expected a pinned host tensor")
+    d = _vp()
+    _check(lib().hh_pinned_device_pointer(_vp(t.data_ptr()), ctypes.byref(d)))
+    return int(d.value)
+
+
+def state_step_raw(states: torch.Tensor, data: torch.Tensor, offsets: int, lengths: int,
+                   width_words: int, out: int, out_words: int, out_offsets: int, state_idx: int,
+                   n: int, stream: int) -> None:
+    """state_step with the item arrays and the output given as device
+    addresses (e.g. from pinned_device_pointer) and an explicit stream
+    handle; states and data are device tensors as for state_step."""
+    _dev(states, "states", _W64, 2)
+    _dev(data, "data", (torch.uint8,), 1)
+    if not (offsets and lengths and width_words and out and out_offsets and state_idx):
+        raise ValueError("every item array must be given")
+    _check(lib().hh_state_step(_ptr(states), states.shape[0], _vp(state_idx), _ptr(data),
+                               data.numel(), _vp(offsets), _vp(lengths), _vp(width_words),
+                               _vp(out), out_words, _vp(out_offsets), n, _vp(stream)))
 
 
 def timing_enable(on: bool = True) -> None:

@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import concurrent.futures
 import dataclasses
 import json
 import sys
@@ -107,9 +108,16 @@ class GpuBackend:
     Admission resets the new states in place.  Per-iteration item lists go
     through a ring of pinned staging buffers so that no copy waits for the
     host, and finished hashes are written compacted in launch order so that
-    one contiguous copy brings them back."""
+    one contiguous copy brings them back.
 
-    RING = 6  # staging sets; more than the scheduler's run-ahead + 1
+    Two lanes: lane 0 launches on the compute stream, lane 1 (the long
+    requests' lane) on a stream of its own with its own staging ring and
+    output buffer, so that a long lane iteration never holds up the short
+    requests' iterations.  Admission runs on the compute stream; the lane 1
+    stream only ever receives that lane's iterations."""
+
+    RING = 6   # staging sets per lane; more than the scheduler's run-ahead + 1
+    LANES = 2
 
     def __init__(self, keys: np.ndarray, payload: np.ndarray, arena_bytes: int, max_slots: int,
                  source: str = "device"):
@@ -120,7 +128,8 @@ class GpuBackend:
         self.keys = torch.from_numpy(np.ascontiguousarray(keys)).view(torch.int64).cuda()
         self.max_slots = max_slots
         self.states = torch.zeros((max_slots, hh.STATE_WORDS), dtype=torch.int64, device="cuda")
-        self.out = torch.zeros((max_slots, 4), dtype=torch.int64, device="cuda")
+        self.out = [torch.zeros((max_slots, 4), dtype=torch.int64, device="cuda")
+                    for _ in range(self.LANES)]
         self.arena = torch.empty(max(arena_bytes, GRANULE), dtype=torch.uint8, device="cuda")
         self.source = source
         src = torch.from_numpy(np.ascontiguousarray(payload))
@@ -133,35 +142,53 @@ class GpuBackend:
             self.ingress.copy_(src)
         self.copy_stream = torch.cuda.Stream()
         self.compute_stream = torch.cuda.current_stream()
+        self.lane_streams = [self.compute_stream, torch.cuda.Stream()]
         # item metadata per staging set: offs u64, lens u64, out offs u64,
         # slots u32, widths u8 for at most max_slots items, each array 8-aligned
         self.meta_bytes = max_slots * (8 + 8 + 8 + 4 + 1) + 64
-        self.h_meta = [torch.empty(self.meta_bytes, dtype=torch.uint8, pin_memory=True)
-                       for _ in range(self.RING)]
-        self.d_meta = [torch.empty(self.meta_bytes, dtype=torch.uint8, device="cuda")
-                       for _ in range(self.RING)]
-        self.h_res = [torch.empty((max_slots, 4), dtype=torch.int64, pin_memory=True)
-                      for _ in range(self.RING)]
+        self.h_meta = [[torch.empty(self.meta_bytes, dtype=torch.uint8, pin_memory=True)
+                        for _ in range(self.RING)] for _ in range(self.LANES)]
+        self.d_meta = [[torch.empty(self.meta_bytes, dtype=torch.uint8, device="cuda")
+                        for _ in range(self.RING)] for _ in range(self.LANES)]
+        self.h_res = [[torch.empty((max_slots, 4), dtype=torch.int64, pin_memory=True)
+                       for _ in range(self.RING)] for _ in range(self.LANES)]
         # admission metadata per staging set: src offs u64, arena offs u64,
         # lens u64, key index u32, slot u32
         self.adm_bytes = max_slots * 32
-        self.h_adm = [torch.empty(self.adm_bytes, dtype=torch.uint8, pin_memory=True)
-                      for _ in range(self.RING)]
-        self.d_adm = [torch.empty(self.adm_bytes, dtype=torch.uint8, device="cuda")
-                      for _ in range(self.RING)]
-        self.k = 0
-        self.ka = 0
+        self.h_adm = [[torch.empty(self.adm_bytes, dtype=torch.uint8, pin_memory=True)
+                       for _ in range(self.RING)] for _ in range(self.LANES)]
+        self.d_adm = [[torch.empty(self.adm_bytes, dtype=torch.uint8, device="cuda")
+                       for _ in range(self.RING)] for _ in range(self.LANES)]
+        self.k = [0] * self.LANES
+        self.ka = [0] * self.LANES
+        # device addresses of the pinned staging and result sets (lane 1
+        # kernels access them directly; lane 0 copies them)
+        self.meta_dev = [[hh.pinned_device_pointer(t) for t in ring] for ring in self.h_meta]
+        self.res_dev = [[hh.pinned_device_pointer(t) for t in ring] for ring in self.h_res]
+        self.launcher = concurrent.futures.ThreadPoolExecutor(max_workers=1)
 
-    def admit(self, reqs: List[Request]) -> None:
+    def admit(self, reqs: List[Request]):
         """Copy the payloads of newly admitted requests into the arena and
-        reset their states in place."""
-        torch = self.torch
+        reset their states in place, on the compute stream.  Returns a ticket
+        for done(): a request of the long lane joins that lane's launches only
+        once its admission has completed, so the lane 1 stream needs no wait
+        on another stream (host-side stream waits, and copies queued on a
+        stream busy with a long iteration, stalled the loop for milliseconds
+        now and then)."""
         if not reqs:
-            return
+            return None
+        self._admit(0, reqs)
+        ev = self.torch.cuda.Event()
+        ev.record(self.compute_stream)
+        return (ev, None)
+
+    def _admit(self, lane: int, reqs: List[Request]) -> None:
+        """Admission work on the current stream, staging ring of `lane`."""
+        torch = self.torch
         n = len(reqs)
-        i = self.ka % self.RING
-        self.ka += 1
-        h = self.h_adm[i].numpy()
+        i = self.ka[lane] % self.RING
+        self.ka[lane] += 1
+        h = self.h_adm[lane][i].numpy()
         src = np.fromiter((r.src for r in reqs), np.int64, n)
         dst = np.fromiter((r.arena_off for r in reqs), np.int64, n)
         lens = np.fromiter((r.length for r in reqs), np.int64, n)
@@ -170,11 +197,11 @@ class GpuBackend:
         h[16 * n:24 * n].view(np.int64)[:] = lens
         h[24 * n:28 * n].view(np.int32)[:] = np.fromiter((r.key_idx for r in reqs), np.int32, n)
         h[28 * n:32 * n].view(np.int32)[:] = np.fromiter((r.slot for r in reqs), np.int32, n)
-        d = self.d_adm[i]
-        d[:32 * n].copy_(self.h_adm[i][:32 * n], non_blocking=True)
+        d = self.d_adm[lane][i]
+        d[:32 * n].copy_(self.h_adm[lane][i][:32 * n], non_blocking=True)
         if self.source == "device":
             # one launch moves every payload, in stream order before the
-            # iteration's updates
+            # lane's next iteration
             self.hh.copy_segments(self.arena, self.ingress, d[:8 * n].view(torch.int64),
                                   d[8 * n:16 * n].view(torch.int64),
                                   d[16 * n:24 * n].view(torch.int64), int(lens.max()))
@@ -186,7 +213,7 @@ class GpuBackend:
                             self.ingress[r.src:r.src + r.length], non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(self.copy_stream)
-            self.compute_stream.wait_event(ev)
+            self.lane_streams[lane].wait_event(ev)
         self.hh.state_init(self.keys, n, d[24 * n:28 * n].view(torch.int32), self.states,
                            d[28 * n:32 * n].view(torch.int32))
 
@@ -197,18 +224,32 @@ class GpuBackend:
         h[off:off + nb] = a.view(np.uint8)
         return off, nb
 
-    def launch(self, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens, fin_widths):
-        """One iteration: fold whole-packet chunks into the states of
-        upd_slots, finish fin_slots, all in one kernel launch.  Arrays of
-        equal length per group.  Returns a ticket for done()/wait()/results()."""
+    def launch(self, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens, fin_widths,
+               lane: int = 0):
+        """One iteration of a lane: fold whole-packet chunks into the states of
+        upd_slots, finish fin_slots, all in one kernel launch on the lane's
+        stream (lane 0: the current stream).  Arrays of equal length per
+        group.  Returns a ticket for done()/wait()/results()."""
+        if lane == 0:
+            return self._launch(0, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens,
+                                fin_widths)
+        # the long lane's launches go through a launcher thread: a launch now
+        # and then holds the calling thread for milliseconds inside the
+        # runtime, which must not stall the scheduling loop (the ctypes call
+        # releases the interpreter lock)
+        return self.launcher.submit(self._launch, lane, upd_slots, upd_offs, upd_lens, fin_slots,
+                                    fin_offs, fin_lens, fin_widths)
+
+    def _launch(self, lane, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens,
+                fin_widths):
         torch, hh = self.torch, self.hh
-        i = self.k % self.RING
-        self.k += 1
+        i = self.k[lane] % self.RING
+        self.k[lane] += 1
         n_upd, n_fin = len(upd_slots), len(fin_slots)
         n = n_upd + n_fin
         res = None
         if n:
-            h = self.h_meta[i].numpy()
+            h = self.h_meta[lane][i].numpy()
             # updates first, then finals; a final's words go to out[4 * j]
             # for its rank j among the finals
             out_offs = np.zeros(n, np.int64)
@@ -226,50 +267,86 @@ class GpuBackend:
                 off = (off + 7) // 8 * 8
                 regs[name] = self._put(h, off, arr, dt)
                 off += regs[name][1]
-            d = self.d_meta[i]
-            d[:off].copy_(self.h_meta[i][:off], non_blocking=True)
+            if lane != 0:
+                # the long lane's kernel reads the item lists from the pinned
+                # staging set and writes the hashes into the pinned result
+                # set: its stream carries no copies (a copy queued behind a
+                # long iteration could hold up the host)
+                mb = self.meta_dev[lane][i]
+                hh.state_step_raw(self.states, self.arena, mb + regs["o"][0], mb + regs["l"][0],
+                                  mb + regs["w"][0], self.res_dev[lane][i],
+                                  self.max_slots * 4, mb + regs["oo"][0], mb + regs["s"][0], n,
+                                  self.lane_streams[lane].cuda_stream)
+                if n_fin:
+                    res = self.h_res[lane][i][:n_fin]
+            else:
+                d = self.d_meta[lane][i]
+                d[:off].copy_(self.h_meta[lane][i][:off], non_blocking=True)
 
-            def view(name, dt):
-                o, nb = regs[name]
-                return d[o:o + nb].view(dt)
+                def view(name, dt):
+                    o, nb = regs[name]
+                    return d[o:o + nb].view(dt)
 
-            hh.state_step(self.states, self.arena, view("o", torch.int64), view("l", torch.int64),
-                          view("w", torch.uint8), self.out.view(-1), view("oo", torch.int64),
-                          view("s", torch.int32))
-            if n_fin:
-                # results land compacted in launch order: one contiguous copy out
-                res = self.h_res[i][:n_fin]
-                res.copy_(self.out[:n_fin], non_blocking=True)
+                out = self.out[lane]
+                hh.state_step(self.states, self.arena, view("o", torch.int64),
+                              view("l", torch.int64), view("w", torch.uint8), out.view(-1),
+                              view("oo", torch.int64), view("s", torch.int32))
+                if n_fin:
+                    # results land compacted in launch order: one contiguous copy out
+                    res = self.h_res[lane][i][:n_fin]
+                    res.copy_(out[:n_fin], non_blocking=True)
         ev = torch.cuda.Event()
-        ev.record(self.compute_stream)
+        ev.record(self.lane_streams[lane])
         return (ev, res)
 
+    @staticmethod
+    def _resolve(ticket):
+        return ticket.result() if isinstance(ticket, concurrent.futures.Future) else ticket
+
     def done(self, ticket) -> bool:
-        return ticket[0].query()
+        if isinstance(ticket, concurrent.futures.Future) and not ticket.done():
+            return False
+        return self._resolve(ticket)[0].query()
 
     def wait(self, ticket) -> None:
-        ticket[0].synchronize()
+        self._resolve(ticket)[0].synchronize()
 
     def results(self, ticket) -> Optional[np.ndarray]:
         """(n_fin, 4) uint64 hash words of the ticket's finished items, in the
         order they were launched."""
-        ev, res = ticket
+        ev, res = self._resolve(ticket)
         return None if res is None else res.numpy().view(np.uint64)
+
+    def close(self) -> None:
+        self.launcher.shutdown(wait=True)
 
 
 class Server:
-    """Scheduler: admission under the budget, chunked continuous batching."""
+    """Scheduler: admission under the budget, chunked continuous batching.
+
+    With a two-lane backend, requests longer than long_min_bytes advance in
+    the long lane, long_chunk_bytes per iteration, on their own stream; the
+    others advance chunk_bytes per iteration in lane 0.  Every lane keeps its
+    own iterations in flight, so the long requests' few large steps never
+    stretch the short requests' iterations."""
 
     def __init__(self, backend, budget_bytes: int, chunk_bytes: int = 1 << 16,
                  max_active: Optional[int] = None, clock=time.perf_counter,
-                 sleep=time.sleep, run_ahead: int = 2):
-        if chunk_bytes <= 0 or chunk_bytes % 32:
-            raise ValueError("chunk_bytes must be a positive multiple of 32")
+                 sleep=time.sleep, run_ahead: int = 2, long_chunk_bytes: int = 1 << 20,
+                 long_min_bytes: Optional[int] = None, poll_s: float = 5e-4):
+        for c in (chunk_bytes, long_chunk_bytes):
+            if c <= 0 or c % 32:
+                raise ValueError("chunk sizes must be positive multiples of 32")
         if run_ahead + 1 >= getattr(backend, "RING", 1 << 30):
             raise ValueError("run_ahead too large for the backend's staging ring")
         self.backend = backend
         self.budget = budget_bytes
         self.chunk = chunk_bytes
+        self.lanes = min(2, getattr(backend, "LANES", 1))
+        self.chunks = [chunk_bytes, long_chunk_bytes]
+        self.long_min = 16 * chunk_bytes if long_min_bytes is None else long_min_bytes
+        self.lane_run_ahead = [run_ahead, 1]
+        self.poll_s = poll_s
         self.arena = Arena(budget_bytes)
         self.max_active = max_active or backend.max_slots
         self.free_slots = list(range(backend.max_slots))[::-1]
@@ -294,7 +371,11 @@ class Server:
         base = np.zeros(S, np.int64)      # arena offset
         width = np.zeros(S, np.uint8)
         owner: List[Optional[Request]] = [None] * S
-        inflight: collections.deque = collections.deque()  # (ticket, finishing slots)
+        lane = np.zeros(S, np.int8)       # lane of the request in the slot
+        ready = np.ones(S, bool)          # admission done (long lane: seen complete)
+        gated: collections.deque = collections.deque()  # (admission ticket, slots)
+        # per lane: (ticket, finishing slots) in launch order
+        inflight = [collections.deque() for _ in range(self.lanes)]
         t0 = self.clock()
         n_total = len(requests)
         self.n_finished = 0
@@ -302,8 +383,8 @@ class Server:
         self.reserved_bytes = 0
         n_busy = 0
 
-        def harvest(block: bool) -> None:
-            ticket, fin = inflight.popleft()
+        def harvest(ln: int, block: bool) -> None:
+            ticket, fin = inflight[ln].popleft()
             if block:
                 self.backend.wait(ticket)
             words = self.backend.results(ticket)
@@ -344,34 +425,59 @@ class Server:
                 self.reserved_bytes += need
                 busy[slot], length[slot], pos[slot] = True, r.length, 0
                 base[slot], width[slot], owner[slot] = off, r.width, r
+                lane[slot] = 1 if (self.lanes > 1 and r.length > self.long_min) else 0
                 n_busy += 1
                 admitted.append(r)
             self.max_bytes_in_flight = max(self.max_bytes_in_flight, self.reserved_bytes)
-            self.backend.admit(admitted)
-            # one chunk for every busy request: whole packets, or its final rest
+            adm = self.backend.admit(admitted)
+            if self.lanes > 1:
+                longs = [r.slot for r in admitted if lane[r.slot] == 1]
+                if longs:
+                    ready[longs] = False
+                    gated.append((adm, longs))
+            # long-lane requests whose admission has completed may advance
+            while gated and self.backend.done(gated[0][0]):
+                ready[gated.popleft()[1]] = True
+            # per lane, one chunk for every busy request of the lane (whole
+            # packets, or its final rest), unless the lane is far enough ahead
             launched = False
-            if n_busy:
-                idx = np.flatnonzero(busy)
+            for ln in range(self.lanes):
+                if len(inflight[ln]) > self.lane_run_ahead[ln]:
+                    continue
+                idx = (np.flatnonzero(busy & (lane == ln) & ready) if self.lanes > 1
+                       else np.flatnonzero(busy))
+                if not idx.size:
+                    continue
+                chunk = self.chunks[ln]
                 rem = length[idx] - pos[idx]
-                fin = rem <= self.chunk
+                fin = rem <= chunk
                 u, f = idx[~fin], idx[fin]
-                ticket = self.backend.launch(u, base[u] + pos[u], np.full(u.size, self.chunk),
-                                             f, base[f] + pos[f], rem[fin], width[f])
-                pos[u] += self.chunk
+                args = (u, base[u] + pos[u], np.full(u.size, chunk), f, base[f] + pos[f],
+                        rem[fin], width[f])
+                ticket = (self.backend.launch(*args, lane=ln) if self.lanes > 1
+                          else self.backend.launch(*args))
+                pos[u] += chunk
                 pos[f] = length[f]
                 busy[f] = False
                 n_busy -= f.size
-                inflight.append((ticket, f))
+                inflight[ln].append((ticket, f))
                 iterations += 1
                 launched = True
-            # harvest what has finished; block when too far ahead or idle
-            while inflight and self.backend.done(inflight[0][0]):
-                harvest(False)
-            while len(inflight) > self.run_ahead:
-                harvest(True)
-            if not launched and inflight:
-                harvest(True)
-            if not n_busy and not inflight and not queue and waiting:
+            # harvest what has finished; lane 0 blocks when too far ahead
+            for ln in range(self.lanes):
+                while inflight[ln] and self.backend.done(inflight[ln][0][0]):
+                    harvest(ln, False)
+            while len(inflight[0]) > self.lane_run_ahead[0]:
+                harvest(0, True)
+            if not launched:
+                if inflight[0]:
+                    harvest(0, True)  # short iterations: wait for the oldest
+                elif (any(inflight) or gated) and not queue:
+                    # only long iterations or admissions in flight: sleep
+                    # until the next arrival (at most poll_s)
+                    nxt = waiting[0].arrival - (self.clock() - t0) if waiting else self.poll_s
+                    self.sleep(max(0.0, min(self.poll_s, nxt)))
+            if not n_busy and not any(inflight) and not gated and not queue and waiting:
                 self.sleep(max(0.0, min(1e-3, waiting[0].arrival - (self.clock() - t0))))
         t_end = self.clock() - t0
         return self.metrics(requests, t_end, iterations)
@@ -403,37 +509,43 @@ def requests_from_trace(trace) -> List[Request]:
 
 
 def serve_trace(trace, budget_bytes: int = 32 << 30, chunk_bytes: int = 1 << 16,
-                max_slots: int = 4096, source: str = "device", time_scale: float = 1.0):
-    """Run one trace on the GPU; returns (metrics, requests)."""
+                max_slots: int = 4096, source: str = "device", time_scale: float = 1.0,
+                **server_kw):
+    """Run one trace on the GPU; returns (metrics, requests).  server_kw go to
+    Server (long_chunk_bytes, long_min_bytes, poll_s, run_ahead)."""
     reqs = requests_from_trace(trace)
     for r in reqs:
         r.arrival *= time_scale
     arena = min(budget_bytes, max(GRANULE, sum(Server.reservation(r.length) for r in reqs)))
     backend = GpuBackend(trace.keys, trace.data, arena, max_slots, source)
     server = Server(backend, budget_bytes=arena if arena < budget_bytes else budget_bytes,
-                    chunk_bytes=chunk_bytes)
-    m = server.run(reqs)
+                    chunk_bytes=chunk_bytes, **server_kw)
+    try:
+        m = server.run(reqs)
+    finally:
+        backend.close()
     m["budget_bytes"] = budget_bytes
     m["source"] = source
     return m, reqs
 
 
 def load_sweep(n_requests: int = 10000, loads=(0.25, 0.5, 0.8), chunk_bytes: int = 1 << 16,
-               budget_bytes: int = 32 << 30, source: str = "device", seed: Optional[int] = None):
+               budget_bytes: int = 32 << 30, source: str = "device", seed: Optional[int] = None,
+               **server_kw):
     """Saturation run (every request arrives at t=0), then Poisson loads at
     the given fractions of the measured saturation request rate."""
     from . import workloads as W
     kw = {} if seed is None else {"seed": seed}
     base = W.serving_trace(n_requests, 1.0, **kw)
     base.arrival_s[:] = 0.0
-    sat, _ = serve_trace(base, budget_bytes, chunk_bytes, source=source)
+    sat, _ = serve_trace(base, budget_bytes, chunk_bytes, source=source, **server_kw)
     sat_rate = sat["requests_per_s"]
     out = [dict(sat, load="saturation", offered_requests_per_s=None)]
     for f in loads:
         tr = W.serving_trace(n_requests, f * sat_rate, materialize=False, **kw)
         tr.data, tr.offsets, tr.lengths = base.data, base.offsets, base.lengths
         tr.key_idx, tr.width_words, tr.keys = base.key_idx, base.width_words, base.keys
-        m, _ = serve_trace(tr, budget_bytes, chunk_bytes, source=source)
+        m, _ = serve_trace(tr, budget_bytes, chunk_bytes, source=source, **server_kw)
         out.append(dict(m, load=f, offered_requests_per_s=f * sat_rate))
     return out
 
@@ -456,9 +568,17 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=1 << 16)
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--source", default="device", choices=["device", "host"])
+    ap.add_argument("--long-chunk", type=int, default=1 << 20)
+    ap.add_argument("--long-min", type=int, default=None,
+                    help="requests longer than this take the long lane (default 16 chunks)")
+    ap.add_argument("--poll-us", type=float, default=500.0)
     args = ap.parse_args(argv)
     loads = tuple(float(x) for x in args.loads.split(",") if x)
-    for p in load_sweep(args.requests, loads, args.chunk, int(args.budget_gib * 2**30), args.source):
+    kw = dict(long_chunk_bytes=args.long_chunk, long_min_bytes=args.long_min,
+              poll_s=args.poll_us * 1e-6)
+    for p in load_sweep(args.requests, loads, args.chunk, int(args.budget_gib * 2**30), args.source,
+                        **kw):
+        p.update({k: v for k, v in kw.items()})
         print(json.dumps(p), flush=True)
 
 

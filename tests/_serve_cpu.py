@@ -22,6 +22,7 @@ class VirtualClock:
 
 class CpuBackend:
     RING = 1 << 30
+    LANES = 2
 
     def __init__(self, keys, payload, arena_bytes, max_slots, clock, ns_per_byte=0.05,
                  launch_s=20e-6):
@@ -35,6 +36,8 @@ class CpuBackend:
         self.cats = {}
         self.live = {}   # slot -> (arena_off, length)
         self.launches = 0
+        self.lane_launches = [0, 0]
+        self.lane_of = {}  # slot -> lane of its first launch
 
     def _check_no_overlap(self):
         spans = sorted((o, o + max(n, 1)) for o, n in self.live.values())
@@ -48,9 +51,17 @@ class CpuBackend:
             self.cats[r.slot] = oracle.Cat(self.keys[r.key_idx])
             self.live[r.slot] = (r.arena_off, r.length)
         self._check_no_overlap()
+        return ("admission",)
 
-    def launch(self, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens, fin_widths):
+    def launch(self, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens, fin_widths,
+               lane=0):
         self.launches += 1
+        self.lane_launches[lane] += 1
+        for slot in list(upd_slots.tolist()) + list(fin_slots.tolist()):
+            # a request stays in one lane for its whole life
+            assert self.lane_of.setdefault(slot, lane) == lane
+        for slot in fin_slots.tolist():
+            del self.lane_of[slot]
         biggest = 0
         for slot, off, n in zip(upd_slots.tolist(), upd_offs.tolist(), upd_lens.tolist()):
             assert n % 32 == 0

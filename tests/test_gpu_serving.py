@@ -17,14 +17,18 @@ def hh():
     return require_gpu()
 
 
-@pytest.mark.parametrize("source", ["device", "host"])
-def test_serving_results_match_alone_and_oracle(hh, source):
-    announce("serving", source)
+@pytest.mark.parametrize("source,long_chunk", [("device", 1 << 20), ("host", 1 << 20),
+                                               ("device", 8192)])
+def test_serving_results_match_alone_and_oracle(hh, source, long_chunk):
+    # requests over 64 KiB take the long lane (its own stream); with 8 KiB
+    # long chunks they run several long-lane iterations beside the short ones
+    announce("serving", source, long_chunk)
     tr = workloads.serving_trace(400, 20000.0, lo=1, hi=200000, n_keys=16, seed=99)
     tr.lengths[::23] = 0
     budget = 8 << 20
     backend = serve.GpuBackend(tr.keys, tr.data, budget, 256, source)
-    srv = serve.Server(backend, budget_bytes=budget, chunk_bytes=4096)
+    srv = serve.Server(backend, budget_bytes=budget, chunk_bytes=4096,
+                       long_chunk_bytes=long_chunk)
     reqs = serve.requests_from_trace(tr)
     m = srv.run(reqs)
     assert m["completed"] == len(reqs)

@@ -93,3 +93,21 @@ def test_chunk_must_be_packet_multiple():
     be = CpuBackend(np.zeros((1, 4), np.uint64), np.zeros(0, np.uint8), 1024, 4, clock)
     with pytest.raises(ValueError):
         serve.Server(be, budget_bytes=1024, chunk_bytes=100)
+
+
+def test_long_lane_results_equal_one_shot():
+    # requests over 2 KiB advance in the long lane, 256 bytes per iteration,
+    # beside the short ones (64 bytes per iteration); every result is exact
+    # and a request never changes lane
+    tr = _trace(200, 3000.0, hi=9000, seed=21)
+    clock = VirtualClock()
+    reqs = serve.requests_from_trace(tr)
+    be = CpuBackend(tr.keys, tr.data, 1 << 17, 64, clock)
+    srv = serve.Server(be, budget_bytes=1 << 17, chunk_bytes=64, long_chunk_bytes=256,
+                       long_min_bytes=2048, clock=clock, sleep=clock.sleep)
+    m = srv.run(reqs)
+    assert m["completed"] == len(reqs)
+    assert be.lane_launches[1] > 0 and be.lane_launches[0] > 0
+    for r in reqs:
+        msg = tr.data[r.src:r.src + r.length]
+        assert r.result == tuple(oracle.hash_words(tr.keys[r.key_idx], msg, r.width)), r.rid
