@@ -3,10 +3,11 @@
 // Two register layouts of the 1024-bit state (Sec. 4.2: v0, v1, mul0, mul1,
 // each four independent 64-bit lanes):
 //
-//   Lanes4 (one thread per message): a thread holds all 16 words.  ZipperMerge
-//     and Permute are pure register renaming plus v_perm_b32; no exchange.
-//   Lane1 (four threads per message, "quad"): thread q of a quad (q = lane id
-//     mod 4) holds lane q of each vector, 4 words.  ZipperMerge of the pair
+//   State4, the thread layout (one thread per message): a thread holds all 16
+//     words.  ZipperMerge and Permute are register renaming plus v_perm_b32;
+//     no exchange.
+//   State1, the quad layout (four threads per message): thread q of a quad
+//     (q = lane id mod 4) holds lane q of each vector, 4 words.  ZipperMerge of the pair
 //     (0,1) / (2,3) needs only the partner's HIGH dword (one DPP move);
 //     Permute needs lane q^2's v0 (two DPP moves).
 //

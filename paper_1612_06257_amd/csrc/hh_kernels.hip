@@ -1,4 +1,5 @@
-// hh_kernels.hip -- HighwayHash kernels for gfx950 and the C ABI of include/hh.h.
+// hh_kernels.hip -- the single-launch HighwayHash kernels for gfx950 and
+// their launchers (the C ABI of include/hh.h is in hh_api.hip).
 //
 // Kernels (all hash exactly the bytes named by offsets/lengths, clamped to the
 // buffer):
@@ -6,8 +7,12 @@
 //                        VGPRs; the plain one-launch kernel.
 //   hh_quad_kernel<W>    four threads per message, one 64-bit lane each;
 //                        shorter dependency chain per packet for long messages.
-//   hh_state_*_kernel    incremental hashing over caller-owned device states.
-// The bucketed planner and persistent kernel live in hh_batched.hip.
+//   hh_prf_kernel<W>     counter-mode PRF: 8-byte counters built in registers.
+//   hh_state_*_kernel    incremental hashing over caller-owned device states
+//                        (reset, update, final, mixed step).
+//   hh_copy_segments_kernel  many byte-segment copies in one launch.
+// The bucketed planner and persistent kernel live in hh_batched.hip, the
+// avalanche statistics in hh_stats.hip.
 
 #include "hh_device.hpp"
 #include "hh_internal.hpp"
