@@ -141,23 +141,55 @@ def time_single_launch(hh, b, dev, path):
     return {"value": b.total_bytes / sec / 1e9, "unit": "GB/s", "ms": sec * 1e3}
 
 
-def cpu_baseline(b, min_seconds: float = 10.0, max_reps: int = 64):
-    """The oracle's threaded batch driver over the whole batch, repeated until
-    at least min_seconds of wall time (a bounded sample of CPU work)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(b, min_seconds: float = 10.0, max_reps: int = 64, single_bytes: int = 1 << 28):
+    """The oracle's threaded batch driver over the whole batch on min(16,
+    cores) threads, repeated until at least min_seconds of wall time (the
+    median run is the value), plus one thread on a bounded sample (the
+    leading messages, about single_bytes, median of 3 runs)."""
+    import numpy as np
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    reps = 0
+    runs = []
     t0 = time.perf_counter()
     while True:
+        t = time.perf_counter()
         ref = oracle.batch(b.keys, b.key_idx, b.data, b.offsets, b.lengths, 1,
                            n_threads=threads)
-        reps += 1
-        sec = time.perf_counter() - t0
-        if sec >= min_seconds or reps >= max_reps:
+        runs.append(time.perf_counter() - t)
+        if time.perf_counter() - t0 >= min_seconds or len(runs) >= max_reps:
             break
-    return {"value": reps * b.total_bytes / sec / 1e9, "unit": "GB/s", "cores": threads,
-            "kind": "oracle", "sample": "the whole batch (%d messages, %d bytes) %d times"
-            % (b.n, b.total_bytes, reps), "seconds": sec}, ref[:, 0]
+    med = float(np.median(runs))
+    # one thread: the leading messages up to about single_bytes
+    lens = b.lengths.astype(np.int64)
+    m = int(np.searchsorted(np.cumsum(lens), single_bytes)) + 1
+    m = max(1, min(m, b.n))
+    sample_bytes = int(lens[:m].sum())
+    ki = None if b.key_idx is None else b.key_idx[:m]
+    one = []
+    for _ in range(3):
+        t = time.perf_counter()
+        oracle.batch(b.keys, ki, b.data, b.offsets[:m], b.lengths[:m], 1, n_threads=1)
+        one.append(time.perf_counter() - t)
+    return {"value": b.total_bytes / med / 1e9, "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "the whole batch (%d messages, %d bytes), %d runs, median"
+            % (b.n, b.total_bytes, len(runs)),
+            "seconds": float(sum(runs)),
+            "single_thread": {"value": sample_bytes / float(np.median(one)) / 1e9,
+                              "unit": "GB/s", "sample": "the first %d messages (%d bytes), "
+                              "3 runs, median" % (m, sample_bytes)},
+            "cpu_model": cpu_model(), "hardware_threads": os.cpu_count()}, ref[:, 0]
 
 
 def load_json(path):
