@@ -166,6 +166,8 @@ class GpuBackend:
         self.meta_dev = [[hh.pinned_device_pointer(t) for t in ring] for ring in self.h_meta]
         self.res_dev = [[hh.pinned_device_pointer(t) for t in ring] for ring in self.h_res]
         self.launcher = concurrent.futures.ThreadPoolExecutor(max_workers=1)
+        self.events = [[torch.cuda.Event() for _ in range(self.RING)] for _ in range(self.LANES)]
+        self.adm_events = [torch.cuda.Event() for _ in range(self.RING)]
 
     def admit(self, reqs: List[Request]):
         """Copy the payloads of newly admitted requests into the arena and
@@ -177,8 +179,12 @@ class GpuBackend:
         now and then)."""
         if not reqs:
             return None
+        i = self.ka[0] % self.RING  # the staging set _admit is about to use
+        # that set's previous admission has finished reading it (normally long
+        # ago; an event never recorded counts as complete)
+        self.adm_events[i].synchronize()
         self._admit(0, reqs)
-        ev = self.torch.cuda.Event()
+        ev = self.adm_events[i]
         ev.record(self.compute_stream)
         return (ev, None)
 
@@ -295,7 +301,9 @@ class GpuBackend:
                     # results land compacted in launch order: one contiguous copy out
                     res = self.h_res[lane][i][:n_fin]
                     res.copy_(out[:n_fin], non_blocking=True)
-        ev = torch.cuda.Event()
+        # events are reused round the staging ring (a set is re-recorded only
+        # after the scheduler has harvested its previous launch)
+        ev = self.events[lane][i]
         ev.record(self.lane_streams[lane])
         return (ev, res)
 
