@@ -21,7 +21,7 @@
 namespace hh {
 
 template <int W>
-__global__ __launch_bounds__(256) void hh_thread_kernel(
+__global__ __launch_bounds__(64) void hh_thread_kernel(
     const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
     const u64* __restrict__ lengths, u64 uniform_length, u64 n, u64* __restrict__ out) {
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void hh_state_step_kernel(
         const bool fin = MODE == 1 || (MODE == 2 && w != 0u);
         const Msg m = message(data, data_bytes, offsets[k], lengths[k]);
         const u32 r = fin ? (u32)(m.len & 31u) : 0u;
-        const u64 tail = r ? remainder_lane(m.p + 32 * (m.len >> 5), r, q) : 0;
+        const u64 tail = r ? remainder_lane(m.p + 32 * (m.len >> 5), r, m.len, q) : 0;
         State1 s;
         load_state1(s, st, q);
         absorb_quad_all<kStateRing>(s, m.p, m.len >> 5, q);
@@ -200,7 +200,8 @@ unsigned grid_for(u64 threads, unsigned block) {
 }  // namespace
 
 hh_status launch_thread(const HashArgs& a, u64 uniform_length, hipStream_t st) {
-    const unsigned block = 256;
+    // one-wave workgroups: a retiring wave frees its slot for the next at once
+    const unsigned block = 64;
     const unsigned grid = grid_for(a.n, block);
     const u64* lengths = a.lengths;
     switch (a.width) {

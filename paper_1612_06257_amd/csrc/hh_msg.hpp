@@ -25,13 +25,13 @@ __device__ __forceinline__ u64 key_index(const u32* key_idx, u32 n_keys, u64 j) 
     return k < n_keys ? k : n_keys - 1u;
 }
 
-// Sec. 4.5 padded remainder packet for the r (1..31) tail bytes at t, as four
-// lanes; loaded before the message's packets are absorbed so that its loads
-// overlap them.
-__device__ __forceinline__ void remainder_packet4(const u8* t, u32 r, u64 pk[4]) {
+// Sec. 4.5 padded remainder packet for the r (1..31) tail bytes at t of a
+// message of len bytes, as four lanes; loaded before the message's packets
+// are absorbed so that its loads overlap them.
+__device__ __forceinline__ void remainder_packet4(const u8* t, u32 r, u64 len, u64 pk[4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        pk[i] = make64(remainder_dword(t, r, 2 * i), remainder_dword(t, r, 2 * i + 1));
+        pk[i] = make64(remainder_dword(t, r, 2 * i, len), remainder_dword(t, r, 2 * i + 1, len));
 }
 
 // Sec. 4.5 remainder step on a whole state held by one thread.
@@ -46,8 +46,8 @@ __device__ __forceinline__ void remainder4(State4& s, u32 r, const u64 pk[4]) {
 }
 
 // Lane q of the Sec. 4.5 padded remainder packet (quad layout).
-__device__ __forceinline__ u64 remainder_lane(const u8* t, u32 r, int q) {
-    return make64(remainder_dword(t, r, 2 * q), remainder_dword(t, r, 2 * q + 1));
+__device__ __forceinline__ u64 remainder_lane(const u8* t, u32 r, u64 len, int q) {
+    return make64(remainder_dword(t, r, 2 * q, len), remainder_dword(t, r, 2 * q + 1, len));
 }
 
 // Sec. 4.5 remainder step, quad layout (thread holds lane q).
@@ -60,24 +60,40 @@ __device__ __forceinline__ void remainder1(State1& s, u32 r, u64 lane_word) {
 // Packets per absorb call: lengths below 2^36 bytes need a single call.
 constexpr u64 kMaxPacketsPerCall = 1ull << 31;
 
-constexpr int kThreadRing = 4;  // packets in flight per thread (thread layout)
+constexpr int kThreadHead = 2;  // packets loaded up front per thread (thread layout)
+constexpr int kThreadRing = 1;  // packets in flight per thread past those (thread layout)
 constexpr int kQuadRing = 12;   // packets in flight per thread (quad layout, wide grids)
 constexpr int kStateRing = 48;  // packets in flight per thread (streaming-state kernels)
 
 // The whole hash of one message in one thread; returns the final lane sums.
+// The tail and the first kThreadHead packets are loaded together before the
+// first Update, so a short message waits for memory once; longer messages
+// continue through a ring of kThreadRing packets.  The small register
+// footprint (about 70 VGPRs) lets six or seven waves share a SIMD, which is
+// what hides the latency of short messages.
 __device__ __forceinline__ void hash_thread(const u64* key, const u8* p, u64 len, u64 sum[4]) {
     const u32 r = (u32)(len & 31u);
     u64 nfull = len >> 5;
     u64 tail[4] = {0, 0, 0, 0};
-    if (r) remainder_packet4(p + 32 * nfull, r, tail);
+    if (r) remainder_packet4(p + 32 * nfull, r, len, tail);
+    Packet head[kThreadHead];
+#pragma unroll
+    for (int k = 0; k < kThreadHead; ++k)
+        if ((u64)k < nfull) head[k] = load_packet(p + 32 * k);
     State4 s;
     reset4(s, key);
-    const u8* cur = p;
-    while (nfull) {
-        const u32 npk = (u32)(nfull < kMaxPacketsPerCall ? nfull : kMaxPacketsPerCall);
-        absorb_thread<kThreadRing>(s, cur, npk);
-        cur += 32 * (u64)npk;
-        nfull -= npk;
+#pragma unroll
+    for (int k = 0; k < kThreadHead; ++k)
+        if ((u64)k < nfull) update4(s, head[k].w);
+    if (nfull > (u64)kThreadHead) {
+        const u8* cur = p + 32 * kThreadHead;
+        nfull -= kThreadHead;
+        while (nfull) {
+            const u32 npk = (u32)(nfull < kMaxPacketsPerCall ? nfull : kMaxPacketsPerCall);
+            absorb_thread<kThreadRing>(s, cur, npk);
+            cur += 32 * (u64)npk;
+            nfull -= npk;
+        }
     }
     if (r) remainder4(s, r, tail);
     finalize4(s, sum);
@@ -101,7 +117,7 @@ template <int RING>
 __device__ __forceinline__ u64 hash_quad(u64 key_q, const u8* p, u64 len, int q) {
     const u32 r = (u32)(len & 31u);
     const u64 nfull = len >> 5;
-    const u64 tail = r ? remainder_lane(p + 32 * nfull, r, q) : 0;
+    const u64 tail = r ? remainder_lane(p + 32 * nfull, r, len, q) : 0;
     State1 s;
     reset1(s, key_q, q);
     absorb_quad_all<RING>(s, p, nfull, q);
