@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kSplitThreads) void hh_split_kernel(
             const u64* kp = keys + 4 * key_index(key_idx, n_keys, j);
             const u64 key[4] = {kp[0], kp[1], kp[2], kp[3]};
             u64 sum[4];
-            hash_thread(key, m.p, m.len, sum);
+            hash_thread<kThreadRing>(key, m.p, m.len, sum);
 #pragma unroll
             for (int i = 0; i < W; ++i) out[(u64)W * j + i] = sum[i];
         }

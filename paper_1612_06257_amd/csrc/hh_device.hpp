@@ -366,19 +366,44 @@ __device__ __forceinline__ Packet load_packet(const u8* p) {
     return r;
 }
 
+// wait_loaded for a whole packet: the compiler may issue its two 16-byte loads
+// in either order, so the asm reads all four words and one s_waitcnt before
+// it covers both loads.
+__device__ __forceinline__ void wait_packet(const Packet& q) {
+    asm volatile("" ::"v"(q.w[0]), "v"(q.w[1]), "v"(q.w[2]), "v"(q.w[3]));
+}
+
+// Whole packets 0..npk-1 (npk >= 1) at p through a thread's state, D packets
+// in flight.  With D = 1 the compiler itself issues the next packet's load
+// ahead of the Update, into other registers.  Deeper rings are laid out by
+// hand like the quad loop: the prologue issues its loads one per scheduling
+// barrier in the loop's order, and each packet gets an explicit wait for its
+// loads, a realignment (align_issue) and then its Update followed by the
+// reload of its registers.  Left to itself the compiler sank a block's loads
+// below its Updates and drained the whole ring at the loop head, so each
+// packet had about one Update, not D, to arrive.
 template <int D>
 __device__ __forceinline__ void absorb_thread(State4& s, const u8* p, u32 npk) {
     const u32 last = npk - 1u;
     Packet ring[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) ring[k] = load_packet(p + 32u * min((u32)k, last));
+    for (int k = 0; k < D; ++k) {
+        ring[k] = load_packet(p + 32u * min((u32)k, last));
+        if constexpr (D > 1) __builtin_amdgcn_sched_barrier(0);
+    }
     u32 t0 = 0;
     for (; t0 + 2u * D < npk; t0 += D) {
         const u8* blk = p + 32u * (t0 + D);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
+            if constexpr (D > 1) {
+                wait_packet(ring[k]);
+                __builtin_amdgcn_sched_barrier(0);
+                align_issue();
+            }
             update4(s, ring[k].w);
             ring[k] = load_packet(blk + 32 * k);
+            if constexpr (D > 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
 #pragma unroll

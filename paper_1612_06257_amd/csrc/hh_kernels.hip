@@ -3,8 +3,10 @@
 //
 // Kernels (all hash exactly the bytes named by offsets/lengths, clamped to the
 // buffer):
-//   hh_thread_kernel<W>  one thread per message, the whole 1024-bit state in
-//                        VGPRs; the plain one-launch kernel.
+//   hh_thread_kernel<W, RING>  one thread per message, the whole 1024-bit
+//                        state in VGPRs; the plain one-launch kernel (RING
+//                        packets in flight: 1 for mixed short batches, 8 for
+//                        uniform lengths of 8 packets or more).
 //   hh_quad_kernel<W>    four threads per message, one 64-bit lane each;
 //                        shorter dependency chain per packet for long messages.
 //   hh_prf_kernel<W>     counter-mode PRF: 8-byte counters built in registers.
@@ -20,7 +22,7 @@
 
 namespace hh {
 
-template <int W>
+template <int W, int RING>
 __global__ __launch_bounds__(64) void hh_thread_kernel(
     const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
@@ -31,7 +33,7 @@ __global__ __launch_bounds__(64) void hh_thread_kernel(
         const u64 key[4] = {kp[0], kp[1], kp[2], kp[3]};
         const Msg m = message(data, data_bytes, offsets[j], lengths ? lengths[j] : uniform_length);
         u64 sum[4];
-        hash_thread(key, m.p, m.len, sum);
+        hash_thread<RING>(key, m.p, m.len, sum);
 #pragma unroll
         for (int i = 0; i < W; ++i) out[(u64)W * j + i] = sum[i];
     }
@@ -199,23 +201,35 @@ unsigned grid_for(u64 threads, unsigned block) {
 
 }  // namespace
 
-hh_status launch_thread(const HashArgs& a, u64 uniform_length, hipStream_t st) {
+template <int RING>
+hh_status launch_thread_ring(const HashArgs& a, u64 uniform_length, hipStream_t st) {
     // one-wave workgroups: a retiring wave frees its slot for the next at once
     const unsigned block = 64;
     const unsigned grid = grid_for(a.n, block);
     const u64* lengths = a.lengths;
     switch (a.width) {
-        case 1: hipLaunchKernelGGL(hh_thread_kernel<1>, dim3(grid), dim3(block), 0, st, a.keys,
-                                   a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, lengths,
-                                   uniform_length, a.n, a.out); break;
-        case 2: hipLaunchKernelGGL(hh_thread_kernel<2>, dim3(grid), dim3(block), 0, st, a.keys,
-                                   a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, lengths,
-                                   uniform_length, a.n, a.out); break;
-        default: hipLaunchKernelGGL(hh_thread_kernel<4>, dim3(grid), dim3(block), 0, st, a.keys,
-                                    a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, lengths,
-                                    uniform_length, a.n, a.out); break;
+        case 1: hipLaunchKernelGGL((hh_thread_kernel<1, RING>), dim3(grid), dim3(block), 0, st,
+                                   a.keys, a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets,
+                                   lengths, uniform_length, a.n, a.out); break;
+        case 2: hipLaunchKernelGGL((hh_thread_kernel<2, RING>), dim3(grid), dim3(block), 0, st,
+                                   a.keys, a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets,
+                                   lengths, uniform_length, a.n, a.out); break;
+        default: hipLaunchKernelGGL((hh_thread_kernel<4, RING>), dim3(grid), dim3(block), 0, st,
+                                    a.keys, a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets,
+                                    lengths, uniform_length, a.n, a.out); break;
     }
     return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+}
+
+// Uniform launches know their length: one of kThreadDeepMinPackets packets or
+// more takes the deep-ring kernel (its few long chains are latency-bound, not
+// occupancy-bound); mixed-length launches take the short-message kernel.
+constexpr u64 kThreadDeepMinPackets = 8;
+
+hh_status launch_thread(const HashArgs& a, u64 uniform_length, hipStream_t st) {
+    if (!a.lengths && (uniform_length >> 5) >= kThreadDeepMinPackets)
+        return launch_thread_ring<kThreadDeepRing>(a, uniform_length, st);
+    return launch_thread_ring<kThreadRing>(a, uniform_length, st);
 }
 
 hh_status launch_quad(const HashArgs& a, hipStream_t st) {

@@ -61,16 +61,20 @@ __device__ __forceinline__ void remainder1(State1& s, u32 r, u64 lane_word) {
 constexpr u64 kMaxPacketsPerCall = 1ull << 31;
 
 constexpr int kThreadHead = 2;  // packets loaded up front per thread (thread layout)
-constexpr int kThreadRing = 1;  // packets in flight per thread past those (thread layout)
+constexpr int kThreadRing = 1;  // packets in flight past those: short messages, many per launch
+constexpr int kThreadDeepRing = 8;  // the same for long messages, few per launch
 constexpr int kQuadRing = 12;   // packets in flight per thread (quad layout, wide grids)
 constexpr int kStateRing = 48;  // packets in flight per thread (streaming-state kernels)
 
 // The whole hash of one message in one thread; returns the final lane sums.
 // The tail and the first kThreadHead packets are loaded together before the
 // first Update, so a short message waits for memory once; longer messages
-// continue through a ring of kThreadRing packets.  The small register
-// footprint (about 70 VGPRs) lets six or seven waves share a SIMD, which is
-// what hides the latency of short messages.
+// continue through a ring of RING packets.  With RING = kThreadRing the small
+// register footprint (under 80 VGPRs) lets six waves share a SIMD, which is
+// what hides the latency of short messages; a long message alone in its wave
+// needs the deeper ring instead, since every 128-byte line it reads from HBM
+// would otherwise stall it for a full memory round trip.
+template <int RING>
 __device__ __forceinline__ void hash_thread(const u64* key, const u8* p, u64 len, u64 sum[4]) {
     const u32 r = (u32)(len & 31u);
     u64 nfull = len >> 5;
@@ -90,7 +94,7 @@ __device__ __forceinline__ void hash_thread(const u64* key, const u8* p, u64 len
         nfull -= kThreadHead;
         while (nfull) {
             const u32 npk = (u32)(nfull < kMaxPacketsPerCall ? nfull : kMaxPacketsPerCall);
-            absorb_thread<kThreadRing>(s, cur, npk);
+            absorb_thread<RING>(s, cur, npk);
             cur += 32 * (u64)npk;
             nfull -= npk;
         }

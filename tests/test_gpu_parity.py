@@ -137,9 +137,13 @@ def test_out_of_contract_inputs_are_clamped(hh):
 
 
 def test_uniform_plain_kernel(hh):
+    # lengths of 8 packets or more take the deep-ring kernel: cover the switch,
+    # every loop/drain boundary of its 8-packet ring after the 2 packets loaded
+    # up front, and a few long lengths
     rng = np.random.default_rng(7)
-    for L in (0, 1, 8, 31, 32, 33, 64, 100, 1024):
-        n = 777
+    deep = [32 * k + r for k in (7, 8, 9, 17, 18, 19, 25, 26, 27, 34, 35, 36) for r in (0, 13)]
+    for L in [0, 1, 8, 31, 32, 33, 64, 100, 1024] + deep + [4097, 65541, 300007]:
+        n = 777 if L <= 4097 else 40
         keys = rng.integers(0, 2**64, size=(4, 4), dtype=np.uint64)
         key_idx = rng.integers(0, 4, n, dtype=np.uint32)
         data = np.frombuffer(rng.bytes(n * L + 3), np.uint8)
