@@ -1,6 +1,7 @@
 """Benchmark: batched HighwayHash-64 on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lognormal]
+                    [--path auto|bucketed|lane1|lane4|prf]
 
 One step = one hh_hash64 call over the whole batch (planner + every hash: key
 setup, packets, remainder, finalization, output), inputs already resident in
@@ -13,9 +14,11 @@ Printed as one JSON line:
   plain        the same batch through the plain one-thread-per-message kernel,
                one launch per distinct length (the baseline the batched path
                is measured against), plus single-launch variants
-  roofline     the dominant kernel (the persistent long-message kernel):
-               algorithmic bytes per launch / its mean duration, timed with
-               HIP events around each launch on the launch stream
+  roofline     the dominant kernel (the persistent long-message kernel on the
+               batched path, else the path's one kernel): algorithmic bytes
+               per launch / its mean duration, timed with HIP events around
+               each launch on the launch stream; valu_roofline the same
+               kernel's counted VALU lane-ops over that duration
   critical_path  the longest message's serial Update chain at the measured
                single-wave Update time
   cpu_baseline the CPU oracle on the host's cores, same batch
@@ -40,8 +43,6 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
 OUT_BYTES = 8                   # HighwayHash-64 result per message
 KEY_BYTES = 32
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILE_DIR, "hh_long_kernel_lognormal_traffic.json")
-VALU_FILE = os.path.join(PROFILE_DIR, "hh_long_kernel_lognormal_valu.json")
 # integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-op per
 # lane per cycle for a full-rate instruction
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -51,13 +52,27 @@ PAPER_CONTEXT = {"cpu": "Xeon E5-2690 v3, one core, 2.6 GHz, AVX2",
                  "cycles_per_byte": {"8": 7.34, "64": 0.95, "1024": 0.24},
                  "GBps_at_1024_bytes": round(2.6 / 0.24, 2)}
 CHAIN_FILE = os.path.join(PROFILE_DIR, "microbench_update_chain.json")
-KERNEL_SOURCES = ["paper_1612_06257_amd/csrc/hh_batched.hip", "paper_1612_06257_amd/csrc/hh_msg.hpp",
-                  "paper_1612_06257_amd/csrc/hh_device.hpp"]
+_CSRC = "paper_1612_06257_amd/csrc/"
+# the sources each kernel is compiled from: their hash gates the reuse of that
+# kernel's counter summaries under profiles/
+KERNEL_SOURCES = {
+    "hh_long_kernel": [_CSRC + "hh_batched.hip", _CSRC + "hh_msg.hpp", _CSRC + "hh_device.hpp"],
+    "hh_thread_kernel": [_CSRC + "hh_kernels.hip", _CSRC + "hh_msg.hpp", _CSRC + "hh_device.hpp"],
+    "hh_quad_kernel": [_CSRC + "hh_kernels.hip", _CSRC + "hh_msg.hpp", _CSRC + "hh_device.hpp"],
+    "hh_prf_kernel": [_CSRC + "hh_kernels.hip", _CSRC + "hh_msg.hpp", _CSRC + "hh_device.hpp"],
+}
+# the kernel that does the hashing on each path
+PATH_KERNEL = {"auto": "hh_long_kernel", "bucketed": "hh_long_kernel",
+               "lane1": "hh_thread_kernel", "lane4": "hh_quad_kernel", "prf": "hh_prf_kernel"}
 
 
-def kernel_source_sha() -> str:
+def profile_file(kernel: str, workload: str, what: str) -> str:
+    return os.path.join(PROFILE_DIR, "%s_%s_%s.json" % (kernel, workload, what))
+
+
+def kernel_source_sha(kernel: str = "hh_long_kernel") -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -212,7 +227,12 @@ def main(argv=None) -> int:
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library defaults instead of the autotuned setting")
+    ap.add_argument("--path", default=None, choices=sorted(PATH_KERNEL),
+                    help="time this path with the library's tuning instead of the autotuned "
+                         "one (prf: the counter-mode kernel, prf_counters workload only)")
     args = ap.parse_args(argv)
+    if args.path == "prf" and args.workload != "prf_counters":
+        ap.error("--path prf needs --workload prf_counters")
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: messages are independent and would shard "
@@ -239,31 +259,50 @@ def main(argv=None) -> int:
     # the timed steps run on a private stream (hipGraph capture needs one)
     stream = torch.cuda.Stream()
     tuned = None
-    path = "auto"
-    if not args.no_autotune:
+    path = args.path or "auto"
+    if not args.no_autotune and args.path is None:
         from paper_1612_06257_amd import autotune
         tuned = autotune.tune(k, d, o, L, ki, 1, cache_path=None)
         path = tuned["path"]
         if path == "bucketed":
             hh.set_tuning(**dict(hh.get_tuning(), **{x: tuned[x] for x in autotune.TUNING_KEYS}))
         print("[bench] autotuned: %s" % json.dumps(tuned), file=sys.stderr, flush=True)
+    kernel = PATH_KERNEL[path]
+
+    def step():
+        if path == "prf":
+            hh.prf(k, b.n, 0, 1, out)
+        else:
+            hh.hash(k, d, o, L, ki, 1, path, out)
+
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
-            hh.hash(k, d, o, L, ki, 1, path, out)
+            step()
         stream.synchronize()
-        # per-launch HIP events around the persistent kernel; they force
-        # direct launches, so the roofline timing is a separate pass
-        hh.timing_enable(True)
-        hh.timing_collect()
-        for _ in range(args.steps):
-            hh.hash(k, d, o, L, ki, 1, path, out)
-        stream.synchronize()
-        launches, long_ms = hh.timing_collect()
-        hh.timing_enable(False)
+        if kernel == "hh_long_kernel":
+            # per-launch HIP events around the persistent kernel; they force
+            # direct launches, so the roofline timing is a separate pass
+            hh.timing_enable(True)
+            hh.timing_collect()
+            for _ in range(args.steps):
+                step()
+            stream.synchronize()
+            launches, kernel_ms = hh.timing_collect()
+            hh.timing_enable(False)
+        else:
+            # one kernel per call: events around each call on this stream
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+            for e0, e1 in ev:
+                e0.record()
+                step()
+                e1.record()
+            stream.synchronize()
+            launches, kernel_ms = args.steps, sum(e0.elapsed_time(e1) for e0, e1 in ev)
         stream.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            hh.hash(k, d, o, L, ki, 1, path, out)
+            step()
         stream.synchronize()
         sec = time.perf_counter() - t0
     ms_per_step = sec * 1e3 / args.steps
@@ -272,34 +311,42 @@ def main(argv=None) -> int:
     print("[bench] batched: %.3f ms/step, %.1f GB/s" % (ms_per_step, value), file=sys.stderr,
           flush=True)
 
-    # roofline of the dominant kernel (persistent long-message kernel)
+    # roofline of the dominant kernel: algorithmic bytes it moves per launch
+    # (message bytes read once, 8 output bytes per message, 32 per key) over
+    # its mean launch time; the PRF reads no message bytes (its counters are
+    # built in registers)
     lengths = b.lengths.astype(np.int64)
-    thr = hh.get_tuning()["lane4_min_bytes"]
-    long_mask = lengths >= thr
-    long_bytes = int(lengths[long_mask].sum()) + OUT_BYTES * int(long_mask.sum()) + KEY_BYTES
-    long_ms_mean = long_ms / launches if launches else None
-    achieved = long_bytes / (long_ms_mean * 1e6) if long_ms_mean else None
+    n_keys = int(b.keys.shape[0])
+    if kernel == "hh_long_kernel":
+        thr = hh.get_tuning()["lane4_min_bytes"]
+        mask = lengths >= thr
+    else:
+        mask = np.ones(lengths.shape, bool)
+    msg_bytes = 0 if kernel == "hh_prf_kernel" else int(lengths[mask].sum())
+    kernel_bytes = msg_bytes + OUT_BYTES * int(mask.sum()) + KEY_BYTES * n_keys
+    kernel_ms_mean = kernel_ms / launches if launches else None
+    achieved = kernel_bytes / (kernel_ms_mean * 1e6) if kernel_ms_mean else None
+    sha = kernel_source_sha(kernel)
     traffic = None
-    tr = load_json(TRAFFIC_FILE)
-    if tr and tr.get("source_sha") == kernel_source_sha() and tr.get("workload") == b.name:
+    tr = load_json(profile_file(kernel, args.workload, "traffic"))
+    if tr and tr.get("source_sha") == sha and tr.get("workload") == b.name:
         traffic = tr.get("hbm_bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": "hh_long_kernel", "achieved": achieved,
+    roofline = {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": traffic,
-                "algorithmic_bytes_per_launch": long_bytes,
-                "kernel_ms_mean": long_ms_mean, "launches_timed": launches}
+                "algorithmic_bytes_per_launch": kernel_bytes,
+                "kernel_ms_mean": kernel_ms_mean, "launches_timed": launches}
     # integer-VALU roof of the same kernel, from its counted VALU instructions
     # (each a wave of 64 lane-ops) over the mean launch time measured above
     valu_roof = None
-    vc = load_json(VALU_FILE)
-    if (vc and vc.get("source_sha") == kernel_source_sha() and vc.get("workload") == b.name
-            and long_ms_mean):
+    vc = load_json(profile_file(kernel, args.workload, "valu"))
+    if vc and vc.get("source_sha") == sha and vc.get("workload") == b.name and kernel_ms_mean:
         c = vc["per_launch"]
         lane_ops = c["SQ_INSTS_VALU"] * 64.0
-        valu_roof = {"bound": "alu", "kernel": "hh_long_kernel",
-                     "achieved": lane_ops / (long_ms_mean * 1e-3) / 1e12,
+        valu_roof = {"bound": "alu", "kernel": kernel,
+                     "achieved": lane_ops / (kernel_ms_mean * 1e-3) / 1e12,
                      "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
-                     "frac": lane_ops / (long_ms_mean * 1e-3) / VALU_PEAK_LANE_OPS,
+                     "frac": lane_ops / (kernel_ms_mean * 1e-3) / VALU_PEAK_LANE_OPS,
                      "valu_insts_per_launch": c["SQ_INSTS_VALU"],
                      "lds_insts_per_launch": c.get("SQ_INSTS_LDS"),
                      "lds_bank_conflict_cycles_per_launch": c.get("SQ_LDS_BANK_CONFLICT")}

@@ -3,7 +3,8 @@
     python -m paper_1612_06257_amd.profiles_summary stats  <kernel_stats.csv> <out.md> <command>
     python -m paper_1612_06257_amd.profiles_summary traffic <fetch.csv> <write.csv> \
         <copy_fetch.csv> <copy_write.csv> <copy_bytes> <workload> <out.json>
-    python -m paper_1612_06257_amd.profiles_summary valu <sq.csv> <workload> <out.json>
+    python -m paper_1612_06257_amd.profiles_summary valu <sq.csv> <workload> <out.json> \
+        [<kernel prefix> [<bench.py arguments of the profiled run>]]
 
 `traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of
 hh_long_kernel by the factor that makes the same counters read the known size
@@ -27,6 +28,11 @@ def kernel_stats(path, out, command):
     open(out, "w").write("\n".join(lines) + "\n")
 
 
+def _base(kernel: str) -> str:
+    """hh::hh_long_kernel<1, 72> -> hh_long_kernel"""
+    return kernel.split("::")[-1].split("<")[0]
+
+
 def _per_kernel(path):
     agg = {}
     for r in csv.DictReader(open(path)):
@@ -47,7 +53,7 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
     f_factor = copy_bytes / (cf * 1024.0)
     w_factor = copy_bytes / (cw * 1024.0)
     rec = {
-        "kernel": kernel, "workload": workload, "source_sha": bench.kernel_source_sha(),
+        "kernel": kernel, "workload": workload, "source_sha": bench.kernel_source_sha(_base(kernel)),
         "fetch_kib_per_dispatch": f[kernel], "write_kib_per_dispatch": w[kernel],
         "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
         "fetch_scale": f_factor, "write_scale": w_factor,
@@ -70,9 +76,12 @@ VALU_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CY
                  "GRBM_GUI_ACTIVE")
 
 
-def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1"):
-    """Per-dispatch means of the SQ counters of the persistent kernel (one
-    rocprofv3 --pmc run with VALU_COUNTERS), with the kernel-source hash."""
+BENCH_ARGS = "--steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving"
+
+
+def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1", bench_args=BENCH_ARGS):
+    """Per-dispatch means of the SQ counters of one kernel (one rocprofv3
+    --pmc run of bench.py with VALU_COUNTERS), with the kernel-source hash."""
     sys.path.insert(0, ".")
     import bench
     per = {}
@@ -81,12 +90,12 @@ def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1"):
         if k.startswith(kernel_prefix):
             per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
             kernel = k
-    rec = {"kernel": kernel, "workload": workload, "source_sha": bench.kernel_source_sha(),
+    rec = {"kernel": kernel, "workload": workload,
+           "source_sha": bench.kernel_source_sha(_base(kernel)),
            "per_launch": {c: sum(v) / len(v) for c, v in sorted(per.items())},
            "launches": len(next(iter(per.values()))),
            "command": "rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " -d <dir> -o bench "
-                      "--output-format csv -- python -u bench.py --steps 2 --warmup 1 "
-                      "--no-cpu-baseline --no-plain --no-autotune --no-serving"}
+                      "--output-format csv -- python -u bench.py " + bench_args}
     json.dump(rec, open(out, "w"), indent=1)
     open(out, "a").write("\n")
     return rec
@@ -96,7 +105,7 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         kernel_stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "valu":
-        print(json.dumps(valu(sys.argv[2], sys.argv[3], sys.argv[4]), indent=1))
+        print(json.dumps(valu(*sys.argv[2:7]), indent=1))
     else:
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5],
                                  int(sys.argv[6]), sys.argv[7], sys.argv[8]), indent=1))
