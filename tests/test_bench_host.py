@@ -1,0 +1,74 @@
+"""Host-side logic of bench.py (no GPU): argument checks, the per-kernel
+source hashes that gate the reuse of counter summaries, and the shape of the
+summaries committed under profiles/."""
+import glob
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + list(args),
+                          capture_output=True, text=True, timeout=120)
+
+
+def test_more_than_one_gpu_is_refused_with_a_reason():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_prf_path_needs_the_prf_workload():
+    r = _run("--path", "prf")
+    assert r.returncode == 2
+    assert "prf_counters" in r.stderr
+
+
+def test_every_path_names_a_kernel_with_sources():
+    for path, kernel in bench.PATH_KERNEL.items():
+        assert kernel in bench.KERNEL_SOURCES, path
+        for rel in bench.KERNEL_SOURCES[kernel]:
+            assert os.path.exists(os.path.join(ROOT, rel)), rel
+
+
+def test_source_hash_is_per_kernel_and_stable():
+    a = bench.kernel_source_sha("hh_long_kernel")
+    assert a == bench.kernel_source_sha("hh_long_kernel")
+    assert len(a) == 16 and int(a, 16) >= 0
+    # the persistent kernel and the single-launch kernels build from
+    # different files, so their hashes differ
+    assert a != bench.kernel_source_sha("hh_thread_kernel")
+    assert bench.kernel_source_sha("hh_thread_kernel") == bench.kernel_source_sha("hh_prf_kernel")
+
+
+def test_workload_names_resolve():
+    for name in ("lognormal", "plain_fixed", "short_mixed", "prf_counters"):
+        assert callable(getattr(__import__("paper_1612_06257_amd.workloads",
+                                           fromlist=[name]), name))
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(ROOT, "profiles", "*_valu.json")) +
+                                        glob.glob(os.path.join(ROOT, "profiles",
+                                                               "*_traffic.json"))))
+def test_committed_counter_summaries_are_well_formed(path):
+    rec = json.load(open(path))
+    base = rec["kernel"].split("::")[-1].split("<")[0]
+    assert base in bench.KERNEL_SOURCES
+    name = os.path.basename(path)
+    assert name.startswith(base + "_")
+    assert len(rec["source_sha"]) == 16
+    assert rec["workload"]
+    if name.endswith("_valu.json"):
+        c = rec["per_launch"]
+        assert c["SQ_INSTS_VALU"] > 0 and c["SQ_WAVES"] > 0
+        assert "rocprofv3 --pmc" in rec["command"]
+    else:
+        assert rec["hbm_bytes_per_launch"] > 0
+        assert 0.5 < rec["fetch_scale"] < 4 and 0.5 < rec["write_scale"] < 4
