@@ -23,6 +23,7 @@ p50/p90/p99 latency.
 from __future__ import annotations
 
 import argparse
+import bisect
 import collections
 import concurrent.futures
 import dataclasses
@@ -58,43 +59,68 @@ class Request:
 
 
 class Arena:
-    """First-fit allocator over [0, capacity) in GRANULE units, coalescing."""
+    """Next-fit allocator over [0, capacity) in GRANULE units, coalescing.
+
+    The search for a free range resumes where the previous allocation ended
+    and wraps around, so with payloads that retire roughly in arrival order
+    the arena behaves like a ring and an allocation rarely looks at more than
+    one free range (a first-fit search from offset 0 walked past every small
+    hole on each admission and dominated the scheduler's host time)."""
 
     def __init__(self, capacity: int):
         self.capacity = capacity // GRANULE * GRANULE
         self.free: List[Tuple[int, int]] = [(0, self.capacity)]  # (offset, size), sorted
         self.used = 0
+        self.rover = 0  # the next search starts at the first range at or past this offset
 
     def alloc(self, nbytes: int) -> Optional[int]:
         n = max(GRANULE, (nbytes + GRANULE - 1) // GRANULE * GRANULE)
-        for i, (off, size) in enumerate(self.free):
+        k = len(self.free)
+        start = bisect.bisect_left(self.free, (self.rover, 0))
+        for j in range(k):
+            i = start + j
+            if i >= k:
+                i -= k
+            off, size = self.free[i]
             if size >= n:
                 if size == n:
                     del self.free[i]
                 else:
                     self.free[i] = (off + n, size - n)
                 self.used += n
+                self.rover = off + n
                 return off
         return None
 
     def release(self, off: int, nbytes: int) -> None:
-        n = max(GRANULE, (nbytes + GRANULE - 1) // GRANULE * GRANULE)
-        self.used -= n
-        lo, hi = 0, len(self.free)
-        while lo < hi:
-            mid = (lo + hi) // 2
-            if self.free[mid][0] < off:
-                lo = mid + 1
+        self.release_many([(off, nbytes)])
+
+    def release_many(self, spans) -> None:
+        """Return (offset, nbytes) spans, coalescing with the free list (one
+        sort-and-merge pass, so a harvest of thousands costs one pass)."""
+        if not spans:
+            return
+        add = [(off, max(GRANULE, (n + GRANULE - 1) // GRANULE * GRANULE)) for off, n in spans]
+        self.used -= sum(n for _, n in add)
+        if len(add) == 1 and len(self.free) > 64:
+            # a lone span: binary search and local merges
+            off, n = add[0]
+            lo = bisect.bisect_left(self.free, (off, 0))
+            self.free.insert(lo, (off, n))
+            if lo + 1 < len(self.free) and off + n == self.free[lo + 1][0]:
+                self.free[lo] = (off, n + self.free[lo + 1][1])
+                del self.free[lo + 1]
+            if lo > 0 and self.free[lo - 1][0] + self.free[lo - 1][1] == self.free[lo][0]:
+                self.free[lo - 1] = (self.free[lo - 1][0], self.free[lo - 1][1] + self.free[lo][1])
+                del self.free[lo]
+            return
+        merged: List[Tuple[int, int]] = []
+        for off, n in sorted(self.free + add):
+            if merged and merged[-1][0] + merged[-1][1] == off:
+                merged[-1] = (merged[-1][0], merged[-1][1] + n)
             else:
-                hi = mid
-        self.free.insert(lo, (off, n))
-        # coalesce with neighbours
-        if lo + 1 < len(self.free) and self.free[lo][0] + self.free[lo][1] == self.free[lo + 1][0]:
-            self.free[lo] = (self.free[lo][0], self.free[lo][1] + self.free[lo + 1][1])
-            del self.free[lo + 1]
-        if lo > 0 and self.free[lo - 1][0] + self.free[lo - 1][1] == self.free[lo][0]:
-            self.free[lo - 1] = (self.free[lo - 1][0], self.free[lo - 1][1] + self.free[lo][1])
-            del self.free[lo]
+                merged.append((off, n))
+        self.free = merged
 
 
 class GpuBackend:
@@ -412,15 +438,18 @@ class Server:
                 self.backend.wait(ticket)
             words = self.backend.results(ticket)
             t = self.clock() - t0
+            rows = words[:, :4].tolist() if len(fin) else []
+            spans = []
             for i, slot in enumerate(fin.tolist()):
                 r = owner[slot]
-                r.result = tuple(int(x) for x in words[i][:r.width])
+                r.result = tuple(rows[i][:r.width])
                 r.t_done, r.status = t, "done"
-                self.arena.release(r.arena_off, max(r.length, 1))
+                spans.append((r.arena_off, max(r.length, 1)))
                 self.reserved_bytes -= r.reserved
                 owner[slot] = None
-                self.free_slots.append(slot)
-                self.n_finished += 1
+            self.arena.release_many(spans)
+            self.free_slots.extend(fin.tolist())
+            self.n_finished += len(fin)
 
         while self.n_finished < n_total:
             now = self.clock() - t0
@@ -446,11 +475,16 @@ class Server:
                 r.arena_off, r.slot, r.reserved = off, slot, need
                 r.status, r.t_admit = "active", now
                 self.reserved_bytes += need
-                busy[slot], length[slot], pos[slot] = True, r.length, 0
-                base[slot], width[slot], owner[slot] = off, r.width, r
-                lane[slot] = 1 if (self.lanes > 1 and r.length > self.long_min) else 0
+                owner[slot] = r
                 n_busy += 1
                 admitted.append(r)
+            if admitted:
+                sl = np.fromiter((r.slot for r in admitted), np.int64, len(admitted))
+                ln = np.fromiter((r.length for r in admitted), np.int64, len(admitted))
+                busy[sl], length[sl], pos[sl] = True, ln, 0
+                base[sl] = np.fromiter((r.arena_off for r in admitted), np.int64, len(admitted))
+                width[sl] = np.fromiter((r.width for r in admitted), np.uint8, len(admitted))
+                lane[sl] = (ln > self.long_min) if self.lanes > 1 else 0
             self.max_bytes_in_flight = max(self.max_bytes_in_flight, self.reserved_bytes)
             adm = self.backend.admit(admitted)
             if self.lanes > 1:

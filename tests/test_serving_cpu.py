@@ -49,6 +49,32 @@ def test_arena_allocator_no_overlap_and_coalesces():
     assert a.free == [(0, a.capacity)] and a.used == 0
 
 
+def test_arena_batched_release_equals_one_by_one():
+    # the scheduler returns a whole harvest at once: the free list after a
+    # batched release equals the one after releasing the same spans singly
+    rng = np.random.default_rng(2)
+    a, b = serve.Arena(1 << 22), serve.Arena(1 << 22)
+    live = []
+    for step in range(3000):
+        if live and rng.random() < 0.4:
+            k = int(rng.integers(1, min(len(live), 40) + 1))
+            idx = set(rng.choice(len(live), k, replace=False).tolist())
+            out = [live[i] for i in sorted(idx)]
+            live = [x for i, x in enumerate(live) if i not in idx]
+            a.release_many(out)
+            for off, n in out:
+                b.release(off, n)
+            assert a.free == b.free and a.used == b.used
+        else:
+            n = int(rng.integers(0, 30000))
+            off_a, off_b = a.alloc(n), b.alloc(n)
+            assert off_a == off_b
+            if off_a is not None:
+                live.append((off_a, n))
+    a.release_many(live)
+    assert a.free == [(0, a.capacity)] and a.used == 0
+
+
 @pytest.mark.parametrize("chunk", [32, 256, 4096])
 def test_results_equal_one_shot_hashes(chunk):
     tr = _trace(250, 2000.0, hi=6000)
