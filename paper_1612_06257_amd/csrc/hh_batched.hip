@@ -33,6 +33,7 @@
 // Messages inside a bucket come out in any order; each message's result only
 // depends on its own bytes, so outputs are deterministic.
 
+#include <list>
 #include <mutex>
 #include <vector>
 
@@ -131,7 +132,8 @@ __global__ __launch_bounds__(kSplitThreads) void hh_split_kernel(
         if (is_long) {
             const u32 rank = __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
-            long_list[wave_base[wave] + rank] = (u32)j;
+            const u32 at = wave_base[wave] + rank;
+            if (at < n) long_list[at] = (u32)j;
             atomicAdd(&hist[bucket_of(packets_capped(m.len))], 1u);
         }
         if (j < n && !is_long) {
@@ -156,7 +158,7 @@ constexpr int kScatterPer = 4;
 __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
     const u64* __restrict__ lengths, Plan* __restrict__ plan, const u32* __restrict__ long_list,
-    u32* __restrict__ order, u32 iso_cap) {
+    u32* __restrict__ order, u32 iso_cap, u32 n) {
     __shared__ u32 cnt[kBuckets];
     __shared__ u32 base[kBuckets];
     __shared__ u32 start[kBuckets];
@@ -190,7 +192,10 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
         }
         __syncthreads();
     }
-    const u32 n_long = plan->n_long;
+    // the plan is this stream's own and zero before the split kernel ran, so
+    // these bounds never bind; they keep every access inside the lists and
+    // the caller's arrays whatever the plan holds
+    const u32 n_long = min(plan->n_long, n);
     const u32 chunk = kScatterPer * 256u;
     for (u32 c0 = blockIdx.x * chunk; c0 < n_long; c0 += gridDim.x * chunk) {
         cnt[threadIdx.x] = 0u;
@@ -200,7 +205,7 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
         for (int k = 0; k < kScatterPer; ++k) {
             const u32 i = c0 + (u32)k * 256u + threadIdx.x;
             bk[k] = kBuckets;
-            if (i < n_long) {
+            if (i < n_long && long_list[i] < n) {
                 jj[k] = long_list[i];
                 const Msg m = message(data, data_bytes, offsets[jj[k]], lengths[jj[k]]);
                 bk[k] = bucket_of(packets_capped(m.len));
@@ -215,7 +220,7 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kScatterPer; ++k)
-            if (bk[k] < kBuckets) order[base[bk[k]] + rk[k]] = jj[k];
+            if (bk[k] < kBuckets && base[bk[k]] + rk[k] < n_long) order[base[bk[k]] + rk[k]] = jj[k];
         __syncthreads();
     }
 }
@@ -248,11 +253,11 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
     const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
     const u8* __restrict__ data, u64 data_bytes, const u64* __restrict__ offsets,
     const u64* __restrict__ lengths, u64* __restrict__ out, Plan* __restrict__ plan,
-    const u32* __restrict__ order) {
+    const u32* __restrict__ order, u32 n) {
     extern __shared__ u32 lds_reserve[];  // sized by the launch to set residency
     const u32 lane = threadIdx.x & 63u;
     const int q = (int)(lane & 3u);
-    const u32 n_long = plan->n_long;
+    const u32 n_long = min(plan->n_long, n);  // never binds (see the scatter kernel)
     const u32 n_items = (n_long + 15u) >> 4;
     const u32 groups = gridDim.x, g = blockIdx.x, w = threadIdx.x >> 6;
     const u32 n_iso = plan->n_iso;  // at most a quarter of the workgroups
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
         const u32 k = 16u * item + (lane >> 2);
         // items come longest first: the item's first message decides whether
         // this wave's chain is long enough to claim its SIMD's issue slots
-        const u32 first = __builtin_amdgcn_readfirstlane(order[16u * item]);
+        const u32 first = min(__builtin_amdgcn_readfirstlane(order[16u * item]), n - 1u);
         if (lengths[first] >= kPriorityBytes)
             __builtin_amdgcn_s_setprio(3);
         else
@@ -281,8 +286,9 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
         // the quads of a ragged last item repeat the item's first message
         // (same cache lines) and store nothing: the wave keeps all lanes on
         {
-            const bool real = k < n_long;
-            const u32 j = order[real ? k : 16u * item];
+            const u32 jk = order[k < n_long ? k : 16u * item];
+            const bool real = k < n_long && jk < n;
+            const u32 j = real ? jk : first;
             const u64 key_q = keys[4 * key_index(key_idx, n_keys, j) + q];
             const Msg m = message(data, data_bytes, offsets[j], lengths[j]);
             const u64 sum = hash_quad<RING>(key_q, m.p, m.len, q);
@@ -308,11 +314,12 @@ struct Workspace {
     Plan* plan;
     u32* long_list;
     u32* order;
-    bool dirty;  // a sequence failed part-way: zero the plan before the next one
+    bool dirty;  // plan not known to be zero (new, or a sequence failed part-way)
 };
 
 std::mutex g_ws_mutex;
-std::vector<Workspace> g_ws;
+// a list: a workspace keeps its address while other threads add theirs
+std::list<Workspace> g_ws;
 
 // measurement hook: event pairs around hh_long_kernel launches
 struct EventPair {
@@ -399,17 +406,15 @@ hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out) {
             (void)hipGetLastError();
             return HH_ERR_OUT_OF_MEMORY;
         }
-        if (hipMemset(mem, 0, plan_bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            (void)hipFree(mem);
-            return HH_ERR_OUT_OF_MEMORY;
-        }
         ws->mem = mem;
         ws->cap_msgs = cap;
         ws->plan = (Plan*)mem;
         ws->long_list = (u32*)(mem + plan_bytes);
         ws->order = (u32*)(mem + plan_bytes + list_bytes);
-        ws->dirty = false;
+        // the first sequence zeroes the plan with a kernel on this stream: a
+        // memset on the null stream is not ordered before work on a
+        // non-blocking stream
+        ws->dirty = true;
     }
     *out = ws;
     return HH_OK;
@@ -444,28 +449,24 @@ LaunchShape launch_shape(const HashArgs& a, const DeviceInfo& di, const hh_tunin
 }
 
 // The launches of one bucketed call: split, scatter, persistent kernel (whose
-// last wave leaves the plan zeroed for the next call; the plan is zeroed
-// when the workspace is allocated, and again by hh_plan_reset_kernel after a
-// sequence that failed part-way).  `ev` (may be null) brackets the
+// last wave leaves the plan zeroed for the next call; launch_bucketed_w runs
+// hh_plan_reset_kernel on the stream before a new workspace's first sequence
+// and after a sequence that failed part-way).  `ev` (may be null) brackets the
 // persistent kernel for the measurement hook.
 template <int W>
 void enqueue_sequence(const HashArgs& a, hipStream_t st, Workspace* ws, const LaunchShape& ls,
                       const hh_tuning& tun, EventPair* ev) {
-    if (ws->dirty) {
-        hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan);
-        ws->dirty = false;
-    }
     hipLaunchKernelGGL(hh_split_kernel<W>, dim3(ls.split_blocks), dim3(kSplitThreads), 0, st, a.keys,
                        a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, a.n, a.out,
                        (u64)tun.lane4_min_bytes, ws->plan, ws->long_list);
     hipLaunchKernelGGL(hh_scatter_kernel, dim3(ls.scatter_blocks), dim3(kBuckets), 0, st, a.data,
                        a.data_bytes, a.offsets, a.lengths, ws->plan, ws->long_list, ws->order,
-                       ls.iso_cap);
+                       ls.iso_cap, (u32)a.n);
     if (ev && hipEventRecord(ev->start, st) != hipSuccess) (void)hipGetLastError();
 #define HH_LONG(RING)                                                                        \
     hipLaunchKernelGGL((hh_long_kernel<W, RING>), dim3(ls.long_blocks), dim3(256), ls.lds, st, \
                        a.keys, a.n_keys, a.key_idx, a.data, a.data_bytes, a.offsets, a.lengths, \
-                       a.out, ws->plan, ws->order)
+                       a.out, ws->plan, ws->order, (u32)a.n)
     switch (tun.long_ring) {
         case 36: HH_LONG(36); break;
         case 48: HH_LONG(48); break;
@@ -562,6 +563,13 @@ template <int W>
 hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, const DeviceInfo& di,
                             const hh_tuning& tun) {
     const LaunchShape ls = launch_shape(a, di, tun);
+    // a plan that is not known to be zero (a new workspace, or a sequence that
+    // failed part-way) is zeroed on this stream first, outside any graph
+    if (ws->dirty) {
+        hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws->plan);
+        if (hipGetLastError() != hipSuccess) return HH_ERR_LAUNCH;
+        ws->dirty = false;
+    }
     EventPair* ev = timing_begin(st);
     hh_status s;
     // the null stream cannot be captured; timed calls launch directly

@@ -159,3 +159,31 @@ def test_back_to_back_calls_share_the_plan(hh):
     torch.cuda.synchronize()
     for i, out in enumerate(outs):
         assert_same(hh.to_u64(out), batches[i % len(batches)][1], "call %d" % i)
+
+
+@pytest.mark.parametrize("n_streams", [2, 3, 4, 6])
+def test_concurrent_calls_on_several_streams(hh, n_streams):
+    # independent batches issued round-robin on several streams overlap on
+    # the GPU; each stream has its own workspace, and a stream's first call
+    # (which zeroes its new plan on that stream) runs while the others are in
+    # flight.  Every call writes its own output; every output is exact.
+    keys, key_idx, data, offsets, lengths = _batch(seed=40 + n_streams, n=1600)
+    base = hh.get_tuning()
+    hh.set_tuning(**dict(base, lane4_min_bytes=0, use_graph=0))
+    try:
+        want = oracle_ref(2, keys, key_idx, data, offsets, lengths)
+        k, ki, d, o, L = batch_to_device(keys, key_idx, data, offsets, lengths)
+        streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        n_calls = 4 * n_streams
+        outs = [torch.full((lengths.size, 2), -1, dtype=torch.int64, device="cuda")
+                for _ in range(n_calls)]
+        torch.cuda.synchronize()
+        announce("concurrent streams", n_streams, n_calls)
+        for i in range(n_calls):
+            with torch.cuda.stream(streams[i % n_streams]):
+                hh.hash(k, d, o, L, ki, 2, "bucketed", outs[i])
+        torch.cuda.synchronize()
+        for i, out in enumerate(outs):
+            assert_same(hh.to_u64(out), want, "streams %d call %d" % (n_streams, i))
+    finally:
+        hh.set_tuning(**base)
