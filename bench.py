@@ -21,6 +21,11 @@ Printed as one JSON line:
                kernel's counted VALU lane-ops over that duration
   critical_path  the longest message's serial Update chain at the measured
                single-wave Update time
+  pipelined    the same steps issued round-robin on 2 and 3 streams (each
+               stream its own workspace and output): independent batches
+               overlap, the next batch's bulk filling the CUs that one
+               batch's few longest chains leave idle; every output is checked
+               against the single-stream result
   cpu_baseline the CPU oracle on the host's cores, same batch
   serving      the serving loop on a 2000-request trace: saturation and 50%
                load, GB/s and p50/p99 request latency (--no-serving skips it)
@@ -351,6 +356,36 @@ def main(argv=None) -> int:
                      "lds_insts_per_launch": c.get("SQ_INSTS_LDS"),
                      "lds_bank_conflict_cycles_per_launch": c.get("SQ_LDS_BANK_CONFLICT")}
 
+    # independent batches on several streams: overlap without changing any
+    # batch's work (bucketed path only; the single-launch kernels fill the
+    # GPU on their own)
+    pipelined = None
+    if kernel == "hh_long_kernel":
+        pipelined = []
+        for n_streams in (2, 3):
+            # streams measured to run concurrently (the runtime shares a few
+            # hardware queues among streams; two on one queue serialise)
+            streams = hh.independent_streams(n_streams, avoid=[])
+            outs = [torch.empty((b.n, 1), dtype=torch.int64, device="cuda")
+                    for _ in range(n_streams)]
+            for s_, o_ in zip(streams, outs):      # each stream's workspace, warm
+                with torch.cuda.stream(s_):
+                    hh.hash(k, d, o, L, ki, 1, path, o_)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                with torch.cuda.stream(streams[i % n_streams]):
+                    hh.hash(k, d, o, L, ki, 1, path, outs[i % n_streams])
+            torch.cuda.synchronize()
+            psec = time.perf_counter() - t0
+            exact = all(np.array_equal(hh.to_u64(x)[:, 0], gpu_hash) for x in outs)
+            pipelined.append({"streams": n_streams, "value": b.total_bytes * args.steps / psec / 1e9,
+                              "unit": "GB/s", "ms_per_batch": psec * 1e3 / args.steps,
+                              "bit_exact": bool(exact)})
+            print("[bench] pipelined on %d streams: %.3f ms/batch, %.1f GB/s" % (
+                n_streams, psec * 1e3 / args.steps, b.total_bytes * args.steps / psec / 1e9),
+                file=sys.stderr, flush=True)
+
     # critical path: longest message x measured single-wave Update time
     chain = load_json(CHAIN_FILE) or {}
     ring = hh.get_tuning()["long_ring"]
@@ -375,6 +410,7 @@ def main(argv=None) -> int:
         "roofline": roofline,
         "valu_roofline": valu_roof,
         "critical_path": critical,
+        "pipelined": pipelined,
         "paper_context": PAPER_CONTEXT,
     }
 

@@ -17,7 +17,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Optional
+from typing import Optional, List
 
 import torch
 
@@ -392,6 +392,66 @@ def pinned_device_pointer(t: torch.Tensor) -> int:
     d = _vp()
     _check(lib().hh_pinned_device_pointer(_vp(t.data_ptr()), ctypes.byref(d)))
     return int(d.value)
+
+
+def independent_streams(n: int, avoid=None, probe_bytes: int = 1 << 22,
+                        max_tries: int = 16) -> List[torch.cuda.Stream]:
+    """n streams whose work runs concurrently with each other and with the
+    streams in `avoid` (default: the current stream).
+
+    The runtime puts streams on a few hardware queues (GPU_MAX_HW_QUEUES,
+    4 by default), which one decided at a stream's first launch by how many
+    streams the process used before; kernels on one queue run in order, so a
+    stream that shares a queue with a busy one waits behind its work.  Each
+    candidate is tested: a one-message hash of probe_bytes (one quad, a few
+    milliseconds) runs on an already chosen or avoided stream, then a tiny
+    kernel on the candidate; the candidate is kept if that kernel completes
+    while the hash still runs.  A candidate's first launch happens here, so
+    its one-time set-up cost is paid here too.  Returns the best streams found
+    if fewer than n independent ones exist."""
+    import time
+    dev = torch.device("cuda", torch.cuda.current_device())
+    busy = list(avoid) if avoid is not None else [torch.cuda.current_stream()]
+    buf = torch.zeros(probe_bytes, dtype=torch.uint8, device=dev)
+    keys = torch.zeros((1, 4), dtype=torch.int64, device=dev)
+    off = torch.zeros(1, dtype=torch.int64, device=dev)
+    ln = torch.full((1,), probe_bytes, dtype=torch.int64, device=dev)
+    out = torch.empty((1, 1), dtype=torch.int64, device=dev)
+    tick = torch.zeros(1, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize(dev)
+
+    def overlaps(cand, other) -> bool:
+        with torch.cuda.stream(other):
+            hash(keys, buf, off, ln, None, 1, "lane4", out)
+            done_other = torch.cuda.Event()
+            done_other.record(other)
+        with torch.cuda.stream(cand):
+            tick.add_(1)
+            done_cand = torch.cuda.Event()
+            done_cand.record(cand)
+        t0 = time.perf_counter()
+        while not done_cand.query() and time.perf_counter() - t0 < 2e-3:
+            time.sleep(5e-5)
+        ok = done_cand.query() and not done_other.query()
+        torch.cuda.synchronize(dev)
+        return ok
+
+    chosen: List[torch.cuda.Stream] = []
+    spare: List[torch.cuda.Stream] = []
+    for _ in range(max_tries):
+        if len(chosen) == n:
+            break
+        cand = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(cand):   # first launch: binds the stream
+            tick.add_(1)
+        torch.cuda.synchronize(dev)
+        if all(overlaps(cand, other) for other in busy + chosen):
+            chosen.append(cand)
+        else:
+            spare.append(cand)
+    while len(chosen) < n and spare:
+        chosen.append(spare.pop(0))
+    return chosen
 
 
 def state_step_raw(states: torch.Tensor, data: torch.Tensor, offsets: int, lengths: int,

@@ -166,9 +166,15 @@ class GpuBackend:
         else:
             self.ingress = torch.empty(src.numel(), dtype=torch.uint8, pin_memory=True)
             self.ingress.copy_(src)
-        self.copy_stream = torch.cuda.Stream()
         self.compute_stream = torch.cuda.current_stream()
-        self.lane_streams = [self.compute_stream, torch.cuda.Stream()]
+        # the long lane (and the host-ingress copies) must not share a
+        # hardware queue with the compute stream, or the short requests'
+        # iterations would wait behind a long iteration: pick streams that are
+        # measured to run concurrently with it
+        extra = hh.independent_streams(2 if source == "host" else 1,
+                                       avoid=[self.compute_stream])
+        self.copy_stream = extra[1] if source == "host" else torch.cuda.Stream()
+        self.lane_streams = [self.compute_stream, extra[0]]
         # item metadata per staging set: offs u64, lens u64, out offs u64,
         # slots u32, widths u8 for at most max_slots items, each array 8-aligned
         self.meta_bytes = max_slots * (8 + 8 + 8 + 4 + 1) + 64
