@@ -187,3 +187,42 @@ def test_concurrent_calls_on_several_streams(hh, n_streams):
             assert_same(hh.to_u64(out), want, "streams %d call %d" % (n_streams, i))
     finally:
         hh.set_tuning(**base)
+
+
+def test_independent_streams_overlap_and_hash_exactly(hh):
+    # streams chosen by measured concurrency: distinct, and a tiny kernel on
+    # one completes while a few-millisecond hash runs on another
+    import time
+    streams = hh.independent_streams(2, avoid=[])
+    assert len(streams) == 2
+    assert streams[0].cuda_stream != streams[1].cuda_stream
+    n = 1 << 22
+    buf = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    keys = torch.zeros((1, 4), dtype=torch.int64, device="cuda")
+    off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ln = torch.full((1,), n, dtype=torch.int64, device="cuda")
+    out = torch.empty((1, 1), dtype=torch.int64, device="cuda")
+    tick = torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(streams[0]):
+        hh.hash(keys, buf, off, ln, None, 1, "lane4", out)
+        e0 = torch.cuda.Event()
+        e0.record()
+    with torch.cuda.stream(streams[1]):
+        tick.add_(1)
+        e1 = torch.cuda.Event()
+        e1.record()
+    t0 = time.perf_counter()
+    while not e1.query() and time.perf_counter() - t0 < 0.5:
+        time.sleep(1e-4)
+    assert e1.query()
+    assert not e0.query(), "the tiny kernel waited for the long hash"
+    torch.cuda.synchronize()
+    keys_, key_idx, data, offsets, lengths = _batch(seed=77, n=600)
+    want = oracle_ref(1, keys_, key_idx, data, offsets, lengths)
+    k, ki, d, o, L = batch_to_device(keys_, key_idx, data, offsets, lengths)
+    for s in streams:
+        with torch.cuda.stream(s):
+            got = hh.hash(k, d, o, L, ki, 1, "bucketed")
+        s.synchronize()
+        assert_same(hh.to_u64(got), want, "stream %x" % s.cuda_stream)
