@@ -27,6 +27,7 @@ import bisect
 import collections
 import concurrent.futures
 import dataclasses
+import itertools
 import json
 import sys
 import time
@@ -414,6 +415,44 @@ class Server:
     def reservation(length: int) -> int:
         return (max(length, 1) + GRANULE - 1) // GRANULE * GRANULE + STATE_BYTES + OUT_BYTES
 
+    def _admit_run(self, queue, owner, admitted, now, n_busy) -> int:
+        """Admit the longest run of queued requests, in arrival order, that
+        the free slots, the budget and one contiguous arena range can take;
+        returns how many (0: leave the head request to the one-at-a-time
+        path, which handles oversized requests, back-pressure and
+        fragmentation).  Same admissions as one at a time, without a Python
+        round of checks per request."""
+        m = min(len(queue), len(self.free_slots), self.max_active - n_busy)
+        if m < 8:
+            return 0
+        cand = list(itertools.islice(queue, m))
+        lens = np.fromiter((r.length for r in cand), np.int64, m)
+        gran = (np.maximum(lens, 1) + GRANULE - 1) // GRANULE * GRANULE
+        need = gran + (STATE_BYTES + OUT_BYTES)
+        over = np.flatnonzero(need > self.budget)
+        if over.size:
+            m = int(over[0])
+        if m == 0:
+            return 0
+        k = int(np.searchsorted(np.cumsum(need[:m]), self.budget - self.reserved_bytes,
+                                side="right"))
+        if k == 0:
+            return 0
+        off = self.arena.alloc(int(gran[:k].sum()))
+        if off is None:
+            return 0
+        offs = (off + np.cumsum(gran[:k]) - gran[:k]).tolist()
+        needs = need[:k].tolist()
+        for i in range(k):
+            r = queue.popleft()
+            slot = self.free_slots.pop()
+            r.arena_off, r.slot, r.reserved = offs[i], slot, needs[i]
+            r.status, r.t_admit = "active", now
+            owner[slot] = r
+        self.reserved_bytes += int(sum(needs))
+        admitted.extend(cand[:k])
+        return k
+
     def run(self, requests: List[Request]) -> dict:
         """Serve `requests`.  Returns the run's metrics."""
         waiting = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -461,9 +500,17 @@ class Server:
             now = self.clock() - t0
             while waiting and waiting[0].arrival <= now:
                 queue.append(waiting.popleft())
-            # admission, in arrival order, while a slot and budget are free
+            # admission, in arrival order, while a slot and budget are free:
+            # runs of requests in bulk, single requests where a run cannot go
             admitted = []
+            bulk = True
             while queue and self.free_slots and n_busy < self.max_active:
+                if bulk:
+                    k = self._admit_run(queue, owner, admitted, now, n_busy)
+                    if k > 0:
+                        n_busy += k
+                        continue
+                    bulk = False
                 r = queue[0]
                 need = self.reservation(r.length)
                 if need > self.budget:
