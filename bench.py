@@ -230,6 +230,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop run")
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the multi-stream run (profiles of the one-stream launches)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library defaults instead of the autotuned setting")
     ap.add_argument("--path", default=None, choices=sorted(PATH_KERNEL),
@@ -360,7 +362,7 @@ def main(argv=None) -> int:
     # batch's work (bucketed path only; the single-launch kernels fill the
     # GPU on their own)
     pipelined = None
-    if kernel == "hh_long_kernel":
+    if kernel == "hh_long_kernel" and not args.no_pipelined:
         pipelined = []
         for n_streams in (2, 3):
             # streams measured to run concurrently (the runtime shares a few

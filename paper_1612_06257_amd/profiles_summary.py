@@ -60,8 +60,8 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
         "hbm_bytes_per_launch": f[kernel] * 1024.0 * f_factor + w[kernel] * 1024.0 * w_factor,
         "other_kernels_fetch_kib": {k: v for k, v in f.items() if k != kernel},
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving",
-            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving",
+            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving --no-pipelined",
+            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving --no-pipelined",
             "rocprofv3 --pmc FETCH_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
             "rocprofv3 --pmc WRITE_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
         ],
@@ -76,7 +76,8 @@ VALU_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CY
                  "GRBM_GUI_ACTIVE")
 
 
-BENCH_ARGS = "--steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving"
+BENCH_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving "
+              "--no-pipelined")
 
 
 def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1", bench_args=BENCH_ARGS):
