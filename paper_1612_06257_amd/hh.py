@@ -454,6 +454,54 @@ def independent_streams(n: int, avoid=None, probe_bytes: int = 1 << 22,
     return chosen
 
 
+_MANY_STREAMS: dict = {}
+
+
+def hash_many(batches, width: int = 1, n_streams: int = 3, path: str = "auto") -> list:
+    """Hash several independent batches, each (keys, data, offsets, lengths,
+    key_idx), round-robin on up to n_streams streams that run concurrently
+    (chosen once per device by independent_streams).  One batch cannot finish
+    before its longest message's serial chain of Updates, which leaves most
+    of the GPU idle for the end of a batch; the next batches fill it.  Work
+    queued on the current stream before the call is visible to every batch,
+    and the current stream waits for all of them; returns the (n_i, width)
+    outputs in order, usable on the current stream."""
+    if width not in (1, 2, 4):
+        raise ValueError("width must be 1, 2 or 4 words")
+    batches = list(batches)
+    if not batches:
+        return []
+    dev = torch.cuda.current_device()
+    streams = _MANY_STREAMS.get((dev, n_streams))
+    if streams is None:
+        streams = independent_streams(n_streams, avoid=[])
+        _MANY_STREAMS[(dev, n_streams)] = streams
+    cur = torch.cuda.current_stream()
+    ready = torch.cuda.Event()
+    ready.record(cur)
+    used = streams[:len(batches)]
+    for s in used:
+        s.wait_event(ready)
+    outs = []
+    for i, (keys, data, offsets, lengths, key_idx) in enumerate(batches):
+        s = used[i % len(used)]
+        with torch.cuda.stream(s):
+            out = torch.empty((offsets.numel(), width), dtype=torch.int64, device=offsets.device)
+            hash(keys, data, offsets, lengths, key_idx, width, path, out)
+        # the caching allocator must not hand these blocks to other work
+        # before the streams that use them are done with them
+        for t in (keys, data, offsets, lengths, key_idx):
+            if t is not None:
+                t.record_stream(s)
+        out.record_stream(cur)
+        outs.append(out)
+    for s in used:
+        done = torch.cuda.Event()
+        done.record(s)
+        cur.wait_event(done)
+    return outs
+
+
 def state_step_raw(states: torch.Tensor, data: torch.Tensor, offsets: int, lengths: int,
                    width_words: int, out: int, out_words: int, out_offsets: int, state_idx: int,
                    n: int, stream: int) -> None:

@@ -226,3 +226,25 @@ def test_independent_streams_overlap_and_hash_exactly(hh):
             got = hh.hash(k, d, o, L, ki, 1, "bucketed")
         s.synchronize()
         assert_same(hh.to_u64(got), want, "stream %x" % s.cuda_stream)
+
+
+def test_hash_many_equals_each_batch_alone(hh):
+    # independent batches of different shapes hashed concurrently on several
+    # streams give exactly what each batch gives alone (and the oracle)
+    batches, wants = [], []
+    for seed, n in ((81, 900), (82, 50), (83, 2500), (84, 1), (85, 700)):
+        keys, key_idx, data, offsets, lengths = _batch(seed=seed, n=max(n, 300))
+        keys_, key_idx_, offsets_, lengths_ = keys, key_idx[:n], offsets[:n], lengths[:n]
+        wants.append(oracle_ref(2, keys_, key_idx_, data, offsets_, lengths_))
+        k, ki, d, o, L = batch_to_device(keys_, key_idx_, data, offsets_, lengths_)
+        batches.append((k, d, o, L, ki))
+    outs = hh.hash_many(batches, width=2, n_streams=3)
+    torch.cuda.synchronize()
+    assert len(outs) == len(batches)
+    for i, (got, want) in enumerate(zip(outs, wants)):
+        assert_same(hh.to_u64(got), want, "batch %d" % i)
+    # twice in a row on the same streams
+    outs2 = hh.hash_many(batches[::-1], width=2, n_streams=3)
+    torch.cuda.synchronize()
+    for i, (got, want) in enumerate(zip(outs2, wants[::-1])):
+        assert_same(hh.to_u64(got), want, "second call batch %d" % i)
