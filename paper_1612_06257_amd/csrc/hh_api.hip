@@ -1,6 +1,7 @@
 // hh_api.hip -- the C ABI declared in include/hh.h: argument checks, device
 // checks and dispatch to the kernel launchers.
 
+#include <atomic>
 #include <mutex>
 #include <string.h>
 
@@ -13,7 +14,8 @@ namespace {
 
 std::mutex g_mutex;
 constexpr int kMaxDevices = 64;
-signed char g_device_ok[kMaxDevices];  // 0 unknown, 1 gfx950, -1 other
+// 0 unknown, 1 gfx950, -1 other; atomic: calls may come from several threads
+std::atomic<signed char> g_device_ok[kMaxDevices];
 hh_tuning g_tuning = {128u, 4u, 0u, 72u, 1u};
 
 hh_status check_hash_args(const HashArgs& a) {
@@ -33,8 +35,9 @@ hh_status check_device(int* device_out) {
         return HH_ERR_UNSUPPORTED_DEVICE;
     }
     if (device_out) *device_out = dev;
-    if (dev < kMaxDevices && g_device_ok[dev] != 0) {
-        return g_device_ok[dev] > 0 ? HH_OK : HH_ERR_UNSUPPORTED_DEVICE;
+    if (dev < kMaxDevices) {
+        const signed char known = g_device_ok[dev].load(std::memory_order_relaxed);
+        if (known != 0) return known > 0 ? HH_OK : HH_ERR_UNSUPPORTED_DEVICE;
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -42,7 +45,7 @@ hh_status check_device(int* device_out) {
         return HH_ERR_UNSUPPORTED_DEVICE;
     }
     const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-    if (dev < kMaxDevices) g_device_ok[dev] = ok ? 1 : -1;
+    if (dev < kMaxDevices) g_device_ok[dev].store(ok ? 1 : -1, std::memory_order_relaxed);
     return ok ? HH_OK : HH_ERR_UNSUPPORTED_DEVICE;
 }
 

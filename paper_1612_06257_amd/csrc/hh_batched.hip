@@ -354,8 +354,10 @@ struct DeviceInfo {
 };
 
 DeviceInfo device_info(int dev) {
+    static std::mutex m;
     static DeviceInfo cache[64];
     static bool have[64];
+    std::lock_guard<std::mutex> lock(m);
     if (dev >= 0 && dev < 64 && have[dev]) return cache[dev];
     DeviceInfo d{0, 0, 0};
     if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||

@@ -248,3 +248,37 @@ def test_hash_many_equals_each_batch_alone(hh):
     torch.cuda.synchronize()
     for i, (got, want) in enumerate(zip(outs2, wants[::-1])):
         assert_same(hh.to_u64(got), want, "second call batch %d" % i)
+
+
+def test_calls_from_several_host_threads(hh):
+    # four host threads, each with its own stream, call the bucketed path at
+    # the same time (ctypes releases the GIL): workspaces are created and
+    # looked up concurrently, every result is exact
+    import threading
+    keys, key_idx, data, offsets, lengths = _batch(seed=91, n=1200)
+    want = oracle_ref(1, keys, key_idx, data, offsets, lengths)
+    k, ki, d, o, L = batch_to_device(keys, key_idx, data, offsets, lengths)
+    results, errors = {}, []
+
+    def work(t):
+        try:
+            s = torch.cuda.Stream()
+            outs = []
+            with torch.cuda.stream(s):
+                for _ in range(5):
+                    outs.append(hh.hash(k, d, o, L, ki, 1, "bucketed"))
+            s.synchronize()
+            results[t] = [hh.to_u64(x) for x in outs]
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=60)
+    assert not errors, errors
+    assert sorted(results) == [0, 1, 2, 3]
+    for t, outs in results.items():
+        for i, got in enumerate(outs):
+            assert_same(got, want, "thread %d call %d" % (t, i))
