@@ -463,6 +463,7 @@ class Server:
         length = np.zeros(S, np.int64)
         pos = np.zeros(S, np.int64)
         base = np.zeros(S, np.int64)      # arena offset
+        resv = np.zeros(S, np.int64)      # budget bytes held
         width = np.zeros(S, np.uint8)
         owner: List[Optional[Request]] = [None] * S
         lane = np.zeros(S, np.int8)       # lane of the request in the slot
@@ -484,15 +485,14 @@ class Server:
             words = self.backend.results(ticket)
             t = self.clock() - t0
             rows = words[:, :4].tolist() if len(fin) else []
-            spans = []
             for i, slot in enumerate(fin.tolist()):
                 r = owner[slot]
                 r.result = tuple(rows[i][:r.width])
                 r.t_done, r.status = t, "done"
-                spans.append((r.arena_off, max(r.length, 1)))
-                self.reserved_bytes -= r.reserved
                 owner[slot] = None
-            self.arena.release_many(spans)
+            self.arena.release_many(list(zip(base[fin].tolist(),
+                                             np.maximum(length[fin], 1).tolist())))
+            self.reserved_bytes -= int(resv[fin].sum())
             self.free_slots.extend(fin.tolist())
             self.n_finished += len(fin)
 
@@ -536,6 +536,7 @@ class Server:
                 ln = np.fromiter((r.length for r in admitted), np.int64, len(admitted))
                 busy[sl], length[sl], pos[sl] = True, ln, 0
                 base[sl] = np.fromiter((r.arena_off for r in admitted), np.int64, len(admitted))
+                resv[sl] = np.fromiter((r.reserved for r in admitted), np.int64, len(admitted))
                 width[sl] = np.fromiter((r.width for r in admitted), np.uint8, len(admitted))
                 lane[sl] = (ln > self.long_min) if self.lanes > 1 else 0
             self.max_bytes_in_flight = max(self.max_bytes_in_flight, self.reserved_bytes)
