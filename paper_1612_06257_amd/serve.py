@@ -27,11 +27,10 @@ import bisect
 import collections
 import concurrent.futures
 import dataclasses
-import itertools
 import json
 import sys
 import time
-from typing import Dict, List, Optional, Tuple
+from typing import Dict, List, NamedTuple, Optional, Tuple
 
 import numpy as np
 
@@ -122,6 +121,20 @@ class Arena:
             else:
                 merged.append((off, n))
         self.free = merged
+
+
+class AdmitBatch(NamedTuple):
+    """Newly admitted requests, as arrays in one order: payload source
+    offset, arena offset, length, key index, state slot."""
+    src: np.ndarray
+    arena_off: np.ndarray
+    length: np.ndarray
+    key_idx: np.ndarray
+    slot: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.slot.size)
 
 
 class GpuBackend:
@@ -217,7 +230,7 @@ class GpuBackend:
             self._warm.add_(1)
         stream.synchronize()
 
-    def admit(self, reqs: List[Request]):
+    def admit(self, batch: AdmitBatch):
         """Copy the payloads of newly admitted requests into the arena and
         reset their states in place, on the compute stream.  Returns a ticket
         for done(): a request of the long lane joins that lane's launches only
@@ -225,32 +238,30 @@ class GpuBackend:
         on another stream (host-side stream waits, and copies queued on a
         stream busy with a long iteration, stalled the loop for milliseconds
         now and then)."""
-        if not reqs:
+        if batch.n == 0:
             return None
         i = self.ka[0] % self.RING  # the staging set _admit is about to use
         # that set's previous admission has finished reading it (normally long
         # ago; an event never recorded counts as complete)
         self.adm_events[i].synchronize()
-        self._admit(0, reqs)
+        self._admit(0, batch)
         ev = self.adm_events[i]
         ev.record(self.compute_stream)
         return (ev, None)
 
-    def _admit(self, lane: int, reqs: List[Request]) -> None:
+    def _admit(self, lane: int, batch: AdmitBatch) -> None:
         """Admission work on the current stream, staging ring of `lane`."""
         torch = self.torch
-        n = len(reqs)
+        n = batch.n
         i = self.ka[lane] % self.RING
         self.ka[lane] += 1
         h = self.h_adm[lane][i].numpy()
-        src = np.fromiter((r.src for r in reqs), np.int64, n)
-        dst = np.fromiter((r.arena_off for r in reqs), np.int64, n)
-        lens = np.fromiter((r.length for r in reqs), np.int64, n)
-        h[:8 * n].view(np.int64)[:] = src
-        h[8 * n:16 * n].view(np.int64)[:] = dst
+        lens = batch.length
+        h[:8 * n].view(np.int64)[:] = batch.src
+        h[8 * n:16 * n].view(np.int64)[:] = batch.arena_off
         h[16 * n:24 * n].view(np.int64)[:] = lens
-        h[24 * n:28 * n].view(np.int32)[:] = np.fromiter((r.key_idx for r in reqs), np.int32, n)
-        h[28 * n:32 * n].view(np.int32)[:] = np.fromiter((r.slot for r in reqs), np.int32, n)
+        h[24 * n:28 * n].view(np.int32)[:] = batch.key_idx
+        h[28 * n:32 * n].view(np.int32)[:] = batch.slot
         d = self.d_adm[lane][i]
         d[:32 * n].copy_(self.h_adm[lane][i][:32 * n], non_blocking=True)
         if self.source == "device":
@@ -261,10 +272,11 @@ class GpuBackend:
                                   d[16 * n:24 * n].view(torch.int64), int(lens.max()))
         else:
             with torch.cuda.stream(self.copy_stream):
-                for r in reqs:
-                    if r.length:
-                        self.arena[r.arena_off:r.arena_off + r.length].copy_(
-                            self.ingress[r.src:r.src + r.length], non_blocking=True)
+                for so, do, ln in zip(batch.src.tolist(), batch.arena_off.tolist(),
+                                      lens.tolist()):
+                    if ln:
+                        self.arena[do:do + ln].copy_(self.ingress[so:so + ln],
+                                                     non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(self.copy_stream)
             self.lane_streams[lane].wait_event(ev)
@@ -415,48 +427,32 @@ class Server:
     def reservation(length: int) -> int:
         return (max(length, 1) + GRANULE - 1) // GRANULE * GRANULE + STATE_BYTES + OUT_BYTES
 
-    def _admit_run(self, queue, owner, admitted, now, n_busy) -> int:
-        """Admit the longest run of queued requests, in arrival order, that
-        the free slots, the budget and one contiguous arena range can take;
-        returns how many (0: leave the head request to the one-at-a-time
-        path, which handles oversized requests, back-pressure and
-        fragmentation).  Same admissions as one at a time, without a Python
-        round of checks per request."""
-        m = min(len(queue), len(self.free_slots), self.max_active - n_busy)
-        if m < 8:
-            return 0
-        cand = list(itertools.islice(queue, m))
-        lens = np.fromiter((r.length for r in cand), np.int64, m)
-        gran = (np.maximum(lens, 1) + GRANULE - 1) // GRANULE * GRANULE
-        need = gran + (STATE_BYTES + OUT_BYTES)
-        over = np.flatnonzero(need > self.budget)
-        if over.size:
-            m = int(over[0])
-        if m == 0:
-            return 0
-        k = int(np.searchsorted(np.cumsum(need[:m]), self.budget - self.reserved_bytes,
-                                side="right"))
-        if k == 0:
-            return 0
-        off = self.arena.alloc(int(gran[:k].sum()))
-        if off is None:
-            return 0
-        offs = (off + np.cumsum(gran[:k]) - gran[:k]).tolist()
-        needs = need[:k].tolist()
-        for i in range(k):
-            r = queue.popleft()
-            slot = self.free_slots.pop()
-            r.arena_off, r.slot, r.reserved = offs[i], slot, needs[i]
-            r.status, r.t_admit = "active", now
-            owner[slot] = r
-        self.reserved_bytes += int(sum(needs))
-        admitted.extend(cand[:k])
-        return k
-
     def run(self, requests: List[Request]) -> dict:
-        """Serve `requests`.  Returns the run's metrics."""
-        waiting = collections.deque(sorted(requests, key=lambda r: r.arrival))
-        queue: collections.deque = collections.deque()   # arrived, not admitted
+        """Serve `requests`.  Returns the run's metrics.
+
+        The loop keeps every request attribute in arrays (arrival order) and
+        does per-iteration work in bulk: the queue is a range of that order,
+        admission takes the longest run of queued requests that the free
+        slots, the budget and one contiguous arena range can hold, and a
+        harvest retires a finished iteration's requests at once.  The Request
+        objects are filled in after the run."""
+        order = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
+        reqs = [requests[i] for i in order]
+        n_total = len(reqs)
+        arrival = np.fromiter((r.arrival for r in reqs), np.float64, n_total)
+        r_len = np.fromiter((r.length for r in reqs), np.int64, n_total)
+        r_width = np.fromiter((r.width for r in reqs), np.int64, n_total)
+        r_key = np.fromiter((r.key_idx for r in reqs), np.int64, n_total)
+        r_src = np.fromiter((r.src for r in reqs), np.int64, n_total)
+        r_gran = (np.maximum(r_len, 1) + GRANULE - 1) // GRANULE * GRANULE
+        r_need = r_gran + (STATE_BYTES + OUT_BYTES)
+        status = np.zeros(n_total, np.int8)        # 0 waiting, 1 active, 2 done, 3 rejected
+        r_slot = np.full(n_total, -1, np.int64)
+        r_off = np.full(n_total, -1, np.int64)
+        r_resv = np.zeros(n_total, np.int64)
+        t_admit = np.full(n_total, -1.0)
+        t_done = np.full(n_total, -1.0)
+        results = np.zeros((n_total, 4), np.uint64)
         S = self.backend.max_slots
         # active set, indexed by state slot
         busy = np.zeros(S, bool)          # admitted, final not yet launched
@@ -465,14 +461,15 @@ class Server:
         base = np.zeros(S, np.int64)      # arena offset
         resv = np.zeros(S, np.int64)      # budget bytes held
         width = np.zeros(S, np.uint8)
-        owner: List[Optional[Request]] = [None] * S
+        owner = np.full(S, -1, np.int64)  # request in the slot
         lane = np.zeros(S, np.int8)       # lane of the request in the slot
         ready = np.ones(S, bool)          # admission done (long lane: seen complete)
         gated: collections.deque = collections.deque()  # (admission ticket, slots)
         # per lane: (ticket, finishing slots) in launch order
         inflight = [collections.deque() for _ in range(self.lanes)]
         t0 = self.clock()
-        n_total = len(requests)
+        arrived = 0   # requests [0, arrived) have arrived
+        head = 0      # requests [head, arrived) are queued
         self.n_finished = 0
         iterations = 0
         self.reserved_bytes = 0
@@ -484,12 +481,13 @@ class Server:
                 self.backend.wait(ticket)
             words = self.backend.results(ticket)
             t = self.clock() - t0
-            rows = words[:, :4].tolist() if len(fin) else []
-            for i, slot in enumerate(fin.tolist()):
-                r = owner[slot]
-                r.result = tuple(rows[i][:r.width])
-                r.t_done, r.status = t, "done"
-                owner[slot] = None
+            if not len(fin):
+                return
+            ridx = owner[fin]
+            results[ridx] = words[:len(fin), :4]
+            t_done[ridx] = t
+            status[ridx] = 2
+            owner[fin] = -1
             self.arena.release_many(list(zip(base[fin].tolist(),
                                              np.maximum(length[fin], 1).tolist())))
             self.reserved_bytes -= int(resv[fin].sum())
@@ -498,54 +496,59 @@ class Server:
 
         while self.n_finished < n_total:
             now = self.clock() - t0
-            while waiting and waiting[0].arrival <= now:
-                queue.append(waiting.popleft())
-            # admission, in arrival order, while a slot and budget are free:
-            # runs of requests in bulk, single requests where a run cannot go
-            admitted = []
-            bulk = True
-            while queue and self.free_slots and n_busy < self.max_active:
-                if bulk:
-                    k = self._admit_run(queue, owner, admitted, now, n_busy)
-                    if k > 0:
-                        n_busy += k
-                        continue
-                    bulk = False
-                r = queue[0]
-                need = self.reservation(r.length)
-                if need > self.budget:
-                    queue.popleft()
-                    r.status, r.t_done = "rejected", now
+            arrived = int(np.searchsorted(arrival, now, side="right"))
+            # admission, in arrival order, while a slot and budget are free
+            runs = []
+            while head < arrived and self.free_slots and n_busy < self.max_active:
+                m = min(arrived - head, len(self.free_slots), self.max_active - n_busy)
+                need = r_need[head:head + m]
+                over = np.flatnonzero(need > self.budget)
+                if over.size and over[0] == 0:
+                    # larger than the whole budget: refused
+                    status[head], t_done[head] = 3, now
                     self.n_finished += 1
+                    head += 1
                     continue
-                if self.reserved_bytes + need > self.budget:
+                if over.size:
+                    m = int(over[0])
+                k = int(np.searchsorted(np.cumsum(need[:m]), self.budget - self.reserved_bytes,
+                                        side="right"))
+                if k == 0:
                     break  # back-pressure: wait for completions
-                off = self.arena.alloc(max(r.length, 1))
+                gran = r_gran[head:head + k]
+                off = self.arena.alloc(int(gran.sum()))
                 if off is None:
-                    break  # fragmented: wait for completions
-                queue.popleft()
-                slot = self.free_slots.pop()
-                r.arena_off, r.slot, r.reserved = off, slot, need
-                r.status, r.t_admit = "active", now
-                self.reserved_bytes += need
-                owner[slot] = r
-                n_busy += 1
-                admitted.append(r)
-            if admitted:
-                sl = np.fromiter((r.slot for r in admitted), np.int64, len(admitted))
-                ln = np.fromiter((r.length for r in admitted), np.int64, len(admitted))
-                busy[sl], length[sl], pos[sl] = True, ln, 0
-                base[sl] = np.fromiter((r.arena_off for r in admitted), np.int64, len(admitted))
-                resv[sl] = np.fromiter((r.reserved for r in admitted), np.int64, len(admitted))
-                width[sl] = np.fromiter((r.width for r in admitted), np.uint8, len(admitted))
-                lane[sl] = (ln > self.long_min) if self.lanes > 1 else 0
+                    # no contiguous range for the run: the head request alone
+                    k, gran = 1, gran[:1]
+                    off = self.arena.alloc(int(gran[0]))
+                    if off is None:
+                        break  # fragmented: wait for completions
+                offs = off + np.cumsum(gran) - gran
+                slots = np.array(self.free_slots[-k:][::-1], np.int64)
+                del self.free_slots[-k:]
+                ridx = np.arange(head, head + k)
+                status[ridx], r_slot[ridx], r_off[ridx] = 1, slots, offs
+                r_resv[ridx], t_admit[ridx] = need[:k], now
+                busy[slots], length[slots], pos[slots] = True, r_len[ridx], 0
+                base[slots], resv[slots], width[slots] = offs, need[:k], r_width[ridx]
+                owner[slots] = ridx
+                lane[slots] = (r_len[ridx] > self.long_min) if self.lanes > 1 else 0
+                self.reserved_bytes += int(need[:k].sum())
+                n_busy += k
+                head += k
+                runs.append(ridx)
             self.max_bytes_in_flight = max(self.max_bytes_in_flight, self.reserved_bytes)
-            adm = self.backend.admit(admitted)
-            if self.lanes > 1:
-                longs = [r.slot for r in admitted if lane[r.slot] == 1]
-                if longs:
-                    ready[longs] = False
-                    gated.append((adm, longs))
+            adm = None
+            if runs:
+                ridx = np.concatenate(runs)
+                adm = self.backend.admit(AdmitBatch(src=r_src[ridx], arena_off=r_off[ridx],
+                                                    length=r_len[ridx], key_idx=r_key[ridx],
+                                                    slot=r_slot[ridx]))
+                if self.lanes > 1:
+                    longs = r_slot[ridx][lane[r_slot[ridx]] == 1]
+                    if longs.size:
+                        ready[longs] = False
+                        gated.append((adm, longs))
             # long-lane requests whose admission has completed may advance
             while gated and self.backend.done(gated[0][0]):
                 ready[gated.popleft()[1]] = True
@@ -583,14 +586,25 @@ class Server:
             if not launched:
                 if inflight[0]:
                     harvest(0, True)  # short iterations: wait for the oldest
-                elif (any(inflight) or gated) and not queue:
+                elif (any(inflight) or gated) and head == arrived:
                     # only long iterations or admissions in flight: sleep
                     # until the next arrival (at most poll_s)
-                    nxt = waiting[0].arrival - (self.clock() - t0) if waiting else self.poll_s
+                    nxt = (arrival[arrived] - (self.clock() - t0) if arrived < n_total
+                           else self.poll_s)
                     self.sleep(max(0.0, min(self.poll_s, nxt)))
-            if not n_busy and not any(inflight) and not gated and not queue and waiting:
-                self.sleep(max(0.0, min(1e-3, waiting[0].arrival - (self.clock() - t0))))
+            if (not n_busy and not any(inflight) and not gated and head == arrived
+                    and arrived < n_total):
+                self.sleep(max(0.0, min(1e-3, arrival[arrived] - (self.clock() - t0))))
         t_end = self.clock() - t0
+        # fill in the Request objects
+        names = {0: "queued", 1: "active", 2: "done", 3: "rejected"}
+        res_rows = results.tolist()
+        for i, r in enumerate(reqs):
+            r.status = names[int(status[i])]
+            r.slot, r.arena_off, r.reserved = int(r_slot[i]), int(r_off[i]), int(r_resv[i])
+            r.t_admit, r.t_done = float(t_admit[i]), float(t_done[i])
+            if status[i] == 2:
+                r.result = tuple(res_rows[i][:r.width])
         return self.metrics(requests, t_end, iterations)
 
     def metrics(self, requests: List[Request], t_end: float, iterations: int) -> dict:

@@ -44,12 +44,14 @@ class CpuBackend:
         for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
             assert a1 <= b0, "arena regions overlap"
 
-    def admit(self, reqs):
-        for r in reqs:
-            assert r.slot not in self.cats, "slot reused while live"
-            self.arena[r.arena_off:r.arena_off + r.length] = self.payload[r.src:r.src + r.length]
-            self.cats[r.slot] = oracle.Cat(self.keys[r.key_idx])
-            self.live[r.slot] = (r.arena_off, r.length)
+    def admit(self, batch):
+        for src, off, n, key, slot in zip(batch.src.tolist(), batch.arena_off.tolist(),
+                                          batch.length.tolist(), batch.key_idx.tolist(),
+                                          batch.slot.tolist()):
+            assert slot not in self.cats, "slot reused while live"
+            self.arena[off:off + n] = self.payload[src:src + n]
+            self.cats[slot] = oracle.Cat(self.keys[key])
+            self.live[slot] = (off, n)
         self._check_no_overlap()
         return ("admission",)
 
