@@ -3,17 +3,21 @@
 A request is (key index, payload bytes, output width 1/2/4 words).  The loop
 keeps every admitted request's 1024-bit state and payload on the device and
 advances all of them together: each scheduler iteration gives every active
-request one chunk (a multiple of 32 bytes, or its whole remainder), launched
-as one streaming-state update and one finalization over all requests.  Only
-size mod 32 enters HighwayHash (Sec. 4.5 of the paper), so a long request
-resumes from its state each iteration and no length counter is kept.
+request of a lane one chunk (a multiple of 32 bytes, or its whole
+remainder), launched as one kernel that mixes the updates and the
+finalizations of the lane's requests.  Requests up to 1 MiB use 64 KiB
+chunks in lane 0; longer ones use 1 MiB chunks in the long lane, on a stream
+of their own.  Only size mod 32 enters HighwayHash (Sec. 4.5 of the paper),
+so a long request resumes from its state each iteration and no length
+counter is kept.
 
 Requests that arrive while others are on the GPU are admitted as soon as a
 state slot and device memory (the admission budget: payload bytes rounded to
 256 plus 128 B of state and 32 B of output) are free, and join the next
-iteration.  The host runs one iteration ahead of the GPU and harvests
+iteration.  The host runs up to two iterations ahead of the GPU and harvests
 completed iterations through events, so admission, chunk planning and
-launches overlap the device work.
+launches overlap the device work; the scheduler keeps its request state in
+arrays and admits and retires requests in bulk.
 
     python -m paper_1612_06257_amd.serve [--requests N] [--loads 0.25,0.5,0.8]
 
@@ -641,7 +645,7 @@ def requests_from_trace(trace) -> List[Request]:
 
 
 def serve_trace(trace, budget_bytes: int = 32 << 30, chunk_bytes: int = 1 << 16,
-                max_slots: int = 4096, source: str = "device", time_scale: float = 1.0,
+                max_slots: int = 16384, source: str = "device", time_scale: float = 1.0,
                 **server_kw):
     """Run one trace on the GPU; returns (metrics, requests).  server_kw go to
     Server (long_chunk_bytes, long_min_bytes, poll_s, run_ahead)."""
