@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
 
 
 def status_string(status: int) -> str:
+    """Text for a status code returned by the library."""
     return lib().hh_status_string(status).decode()
 
 
@@ -169,14 +170,17 @@ def hash(keys: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor, lengths:
 
 
 def hash64(keys, data, offsets, lengths, key_idx=None, out=None) -> torch.Tensor:
+    """hash(..., width=1) on the AUTO path: one 64-bit word per message."""
     return hash(keys, data, offsets, lengths, key_idx, 1, "auto", out)
 
 
 def hash128(keys, data, offsets, lengths, key_idx=None, out=None) -> torch.Tensor:
+    """hash(..., width=2) on the AUTO path: two 64-bit words per message."""
     return hash(keys, data, offsets, lengths, key_idx, 2, "auto", out)
 
 
 def hash256(keys, data, offsets, lengths, key_idx=None, out=None) -> torch.Tensor:
+    """hash(..., width=4) on the AUTO path: four 64-bit words per message."""
     return hash(keys, data, offsets, lengths, key_idx, 4, "auto", out)
 
 
@@ -368,12 +372,14 @@ def constants():
 
 
 def get_tuning() -> dict:
+    """The library's tuning of the bucketed path, as a dict of hh_tuning fields."""
     t = _Tuning()
     lib().hh_get_tuning(ctypes.byref(t))
     return {f: int(getattr(t, f)) for f, _ in _Tuning._fields_}
 
 
 def set_tuning(**kw) -> None:
+    """Set the given hh_tuning fields (the others keep their values); invalid values raise."""
     cur = get_tuning()
     cur.update(kw)
     t = _Tuning(**cur)
@@ -381,6 +387,7 @@ def set_tuning(**kw) -> None:
 
 
 def release() -> None:
+    """Free the library's per-stream workspaces and cached graphs (no call may be in flight)."""
     _check(lib().hh_release())
 
 
