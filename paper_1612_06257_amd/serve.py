@@ -708,10 +708,14 @@ def main(argv=None):
     ap.add_argument("--long-min", type=int, default=None,
                     help="requests longer than this take the long lane (default 16 chunks)")
     ap.add_argument("--poll-us", type=float, default=500.0)
+    ap.add_argument("--max-slots", type=int, default=16384,
+                    help="request states held on the device (128 B each)")
     args = ap.parse_args(argv)
+    if args.max_slots < 1:
+        ap.error("--max-slots must be at least 1")
     loads = tuple(float(x) for x in args.loads.split(",") if x)
     kw = dict(long_chunk_bytes=args.long_chunk, long_min_bytes=args.long_min,
-              poll_s=args.poll_us * 1e-6)
+              poll_s=args.poll_us * 1e-6, max_slots=args.max_slots)
     for p in load_sweep(args.requests, loads, args.chunk, int(args.budget_gib * 2**30), args.source,
                         **kw):
         p.update({k: v for k, v in kw.items()})
