@@ -57,8 +57,11 @@ __device__ __forceinline__ void remainder1(State1& s, u32 r, u64 lane_word) {
     update1(s, lane_word);
 }
 
-// Packets per absorb call: lengths below 2^36 bytes need a single call.
-constexpr u64 kMaxPacketsPerCall = 1ull << 31;
+// Packets per absorb call.  Inside a call the loops form byte offsets as
+// 32 * packet index in 32-bit arithmetic (one VALU op per address), so a call
+// covers at most 4 GiB; longer messages take several calls, each starting
+// from a 64-bit pointer.
+constexpr u64 kMaxPacketsPerCall = 1ull << 27;
 
 constexpr int kThreadHead = 2;  // packets loaded up front per thread (thread layout)
 constexpr int kThreadRing = 1;  // packets in flight past those: short messages, many per launch
