@@ -22,7 +22,8 @@
  *   - A key is four uint64 words; word i is lane i (a 32-byte key read
  *     little-endian).  keys[4*k + i] is lane i of key k.
  *   - Message j is data[offsets[j] .. offsets[j] + lengths[j]), bytes at any
- *     alignment; offsets[j] + lengths[j] <= data_bytes is the caller's
+ *     alignment and of any 64-bit length (offsets and messages beyond 4 GiB
+ *     included); offsets[j] + lengths[j] <= data_bytes is the caller's
  *     contract.  The kernels never read outside [data, data + data_bytes)
  *     rounded out to whole 4-byte words: a message that violates the contract
  *     is clamped to the buffer and hashed truncated, it never faults.
