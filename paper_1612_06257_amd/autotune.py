@@ -3,7 +3,9 @@
 For a batch (device tensors as for ``hh.hash``) it times candidate settings of
 the bucketed path -- split threshold (which messages get four threads each),
 persistent residency (waves per CU), prefetch ring depth, hipGraph replay --
-and the two single-launch kernels, and keeps the fastest.  Results are cached
+and the two single-launch kernels, and keeps the fastest unless the library
+defaults are within a small margin of it (the minimum of many noisy timings
+beats any fixed setting by about that much on its own).  Results are cached
 in a JSON file keyed by device architecture, CU count, output width and a
 signature of the batch (message count and the log2 buckets of the mean and
 maximum length), so a later batch of the same shape reuses them.
@@ -88,10 +90,31 @@ def candidates():
     yield {"path": "lane4"}
 
 
+# a candidate replaces the defaults only if it is faster by more than this
+# fraction: run-to-run spread of one batch's time is about 1%
+DEFAULT_MARGIN = 0.02
+
+
+def pick(results, defaults: dict, margin: float = DEFAULT_MARGIN):
+    """(seconds, candidate) of the choice among the timed (seconds, candidate)
+    pairs: the fastest, unless the bucketed path with the `defaults` tuning is
+    within `margin` of it; also returns the defaults' time (None if they were
+    not timed)."""
+    if not results:
+        raise ValueError("no timed candidates")
+    best = min(results, key=lambda r: r[0])
+    default = next((r for r in results if r[1]["path"] == "bucketed" and all(
+        r[1][k] == defaults[k] for k in TUNING_KEYS)), None)
+    if default is not None and best[0] >= default[0] * (1.0 - margin):
+        best = default
+    return best[0], best[1], None if default is None else default[0]
+
+
 def tune(keys, data, offsets, lengths, key_idx=None, width: int = 1, reps: int = 5,
-         cache_path: Optional[str] = DEFAULT_CACHE, verbose: bool = False) -> dict:
+         cache_path: Optional[str] = DEFAULT_CACHE, verbose: bool = False,
+         margin: float = DEFAULT_MARGIN) -> dict:
     """Time every candidate on this batch (on a private stream, so that
-    hipGraph capture is possible) and cache the fastest; returns it."""
+    hipGraph capture is possible) and cache the choice of `pick`; returns it."""
     saved = hh.get_tuning()
     out = torch.empty((offsets.numel(), width), dtype=torch.int64, device=offsets.device)
     results = []
@@ -108,11 +131,10 @@ def tune(keys, data, offsets, lengths, key_idx=None, width: int = 1, reps: int =
                     print("autotune %.4f ms %s" % (sec * 1e3, c), flush=True)
     finally:
         hh.set_tuning(**saved)
-    sec, best = min(results, key=lambda r: r[0])
-    default = next((s for s, c in results if c["path"] == "bucketed" and all(
-        c[k] == saved[k] for k in TUNING_KEYS)), None)
+    sec, best, default = pick(results, saved, margin)
+    fastest = min(r[0] for r in results)
     entry = dict(best, ms=sec * 1e3, default_ms=None if default is None else default * 1e3,
-                 candidates=len(results))
+                 fastest_ms=fastest * 1e3, margin=margin, candidates=len(results))
     if cache_path:
         cache = _load(cache_path)
         cache[signature(lengths, width)] = entry

@@ -1,0 +1,54 @@
+"""The autotuner's choice among timed candidates (no GPU): the fastest wins
+only when it beats the library defaults by more than the margin."""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+from paper_1612_06257_amd import autotune  # noqa: E402
+
+DEFAULTS = {"long_ring": 72, "waves_per_cu": 4, "lane4_min_bytes": 0, "use_graph": 0,
+            "isolate_long": 1}
+
+
+def _bucketed(**kw):
+    return dict(dict(DEFAULTS, **kw), path="bucketed")
+
+
+def test_candidate_set_is_the_documented_one():
+    cands = list(autotune.candidates())
+    bucketed = [c for c in cands if c["path"] == "bucketed"]
+    assert len(bucketed) == 72 and len(cands) == 74
+    assert all(c["waves_per_cu"] == 4 for c in bucketed if c["isolate_long"])
+    assert _bucketed() in cands
+
+
+def test_defaults_kept_within_the_margin():
+    res = [(1.000, _bucketed()), (0.990, _bucketed(long_ring=96)), (1.5, {"path": "lane4"})]
+    sec, best, default = autotune.pick(res, DEFAULTS, margin=0.02)
+    assert best == _bucketed() and sec == 1.000 and default == 1.000
+
+
+def test_clearly_faster_candidate_wins():
+    res = [(1.000, _bucketed()), (0.900, _bucketed(waves_per_cu=8, isolate_long=0)),
+           (0.950, {"path": "lane1"})]
+    sec, best, default = autotune.pick(res, DEFAULTS, margin=0.02)
+    assert best == _bucketed(waves_per_cu=8, isolate_long=0) and sec == 0.900
+    assert default == 1.000
+
+
+def test_fastest_wins_when_defaults_were_not_timed():
+    res = [(1.000, _bucketed(long_ring=48)), (0.995, _bucketed(long_ring=96))]
+    sec, best, default = autotune.pick(res, DEFAULTS, margin=0.02)
+    assert best["long_ring"] == 96 and default is None
+
+
+def test_zero_margin_is_the_plain_minimum():
+    res = [(1.000, _bucketed()), (0.999, _bucketed(long_ring=96))]
+    assert autotune.pick(res, DEFAULTS, margin=0.0)[1]["long_ring"] == 96
+
+
+def test_no_candidates_is_an_error():
+    with pytest.raises(ValueError):
+        autotune.pick([], DEFAULTS)
