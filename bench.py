@@ -71,6 +71,40 @@ PATH_KERNEL = {"auto": "hh_long_kernel", "bucketed": "hh_long_kernel",
                "lane1": "hh_thread_kernel", "lane4": "hh_quad_kernel", "prf": "hh_prf_kernel"}
 
 
+TUNING_KEYS = ("lane4_min_bytes", "waves_per_cu", "use_graph", "long_ring", "isolate_long")
+
+
+def parse_tuning(text: str) -> dict:
+    """hh_tuning fields from a JSON object; unknown fields or non-integer
+    values raise ValueError (the library checks the ranges)."""
+    try:
+        t = json.loads(text)
+    except ValueError as e:
+        raise ValueError("not JSON: %s" % e)
+    if not isinstance(t, dict) or not t:
+        raise ValueError("expected a JSON object of hh_tuning fields")
+    bad = sorted(set(t) - set(TUNING_KEYS))
+    if bad:
+        raise ValueError("unknown fields %s (known: %s)" % (bad, ", ".join(TUNING_KEYS)))
+    if not all(isinstance(v, int) and not isinstance(v, bool) for v in t.values()):
+        raise ValueError("values must be integers")
+    return t
+
+
+def profile_applies(rec, kernel: str, workload_name: str, tuning: dict) -> bool:
+    """A committed counter summary describes the timed launches only if it
+    was taken from the same kernel sources on the same workload and, for the
+    bucketed path's kernel (the only one the tuning changes), with the same
+    tuning."""
+    if not rec or rec.get("source_sha") != kernel_source_sha(kernel):
+        return False
+    if rec.get("workload") != workload_name:
+        return False
+    if kernel == "hh_long_kernel":
+        return rec.get("tuning") == {k: tuning[k] for k in TUNING_KEYS}
+    return True
+
+
 def profile_file(kernel: str, workload: str, what: str) -> str:
     return os.path.join(PROFILE_DIR, "%s_%s_%s.json" % (kernel, workload, what))
 
@@ -234,12 +268,21 @@ def main(argv=None) -> int:
                     help="skip the multi-stream run (profiles of the one-stream launches)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library defaults instead of the autotuned setting")
+    ap.add_argument("--tuning", default=None, metavar="JSON",
+                    help="time the bucketed path with these hh_tuning fields (the others "
+                         "keep the library defaults) instead of the autotuned setting")
     ap.add_argument("--path", default=None, choices=sorted(PATH_KERNEL),
                     help="time this path with the library's tuning instead of the autotuned "
                          "one (prf: the counter-mode kernel, prf_counters workload only)")
     args = ap.parse_args(argv)
     if args.path == "prf" and args.workload != "prf_counters":
         ap.error("--path prf needs --workload prf_counters")
+    fixed_tuning = None
+    if args.tuning is not None:
+        try:
+            fixed_tuning = parse_tuning(args.tuning)
+        except ValueError as e:
+            ap.error("--tuning: %s" % e)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: messages are independent and would shard "
@@ -267,7 +310,10 @@ def main(argv=None) -> int:
     stream = torch.cuda.Stream()
     tuned = None
     path = args.path or "auto"
-    if not args.no_autotune and args.path is None:
+    if fixed_tuning is not None:
+        hh.set_tuning(**dict(hh.get_tuning(), **fixed_tuning))
+        tuned = {"fixed": fixed_tuning}
+    elif not args.no_autotune and args.path is None:
         from paper_1612_06257_amd import autotune
         tuned = autotune.tune(k, d, o, L, ki, 1, cache_path=None)
         path = tuned["path"]
@@ -333,10 +379,10 @@ def main(argv=None) -> int:
     kernel_bytes = msg_bytes + OUT_BYTES * int(mask.sum()) + KEY_BYTES * n_keys
     kernel_ms_mean = kernel_ms / launches if launches else None
     achieved = kernel_bytes / (kernel_ms_mean * 1e6) if kernel_ms_mean else None
-    sha = kernel_source_sha(kernel)
+    timed_tuning = hh.get_tuning()
     traffic = None
     tr = load_json(profile_file(kernel, args.workload, "traffic"))
-    if tr and tr.get("source_sha") == sha and tr.get("workload") == b.name:
+    if profile_applies(tr, kernel, b.name, timed_tuning):
         traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -347,7 +393,7 @@ def main(argv=None) -> int:
     # (each a wave of 64 lane-ops) over the mean launch time measured above
     valu_roof = None
     vc = load_json(profile_file(kernel, args.workload, "valu"))
-    if vc and vc.get("source_sha") == sha and vc.get("workload") == b.name and kernel_ms_mean:
+    if profile_applies(vc, kernel, b.name, timed_tuning) and kernel_ms_mean:
         c = vc["per_launch"]
         lane_ops = c["SQ_INSTS_VALU"] * 64.0
         valu_roof = {"bound": "alu", "kernel": kernel,

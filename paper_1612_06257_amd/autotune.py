@@ -3,9 +3,9 @@
 For a batch (device tensors as for ``hh.hash``) it times candidate settings of
 the bucketed path -- split threshold (which messages get four threads each),
 persistent residency (waves per CU), prefetch ring depth, hipGraph replay --
-and the two single-launch kernels, and keeps the fastest unless the library
-defaults are within a small margin of it (the minimum of many noisy timings
-beats any fixed setting by about that much on its own).  Results are cached
+and the two single-launch kernels, re-times the leaders and the defaults, and
+keeps, of the settings within a small margin of the fastest, the one closest
+to the library defaults.  Results are cached
 in a JSON file keyed by device architecture, CU count, output width and a
 signature of the batch (message count and the log2 buckets of the mean and
 maximum length), so a later batch of the same shape reuses them.
@@ -90,23 +90,35 @@ def candidates():
     yield {"path": "lane4"}
 
 
-# a candidate replaces the defaults only if it is faster by more than this
-# fraction: run-to-run spread of one batch's time is about 1%
-DEFAULT_MARGIN = 0.02
+# Candidates within this fraction of the fastest, as timed in the confirming
+# round, count as equally fast; of those the one closest to the library
+# defaults is kept.  The first round times every candidate briefly and its
+# minimum is biased low (the least of 74 noisy timings); the confirming round
+# re-times the leaders and the defaults, interleaved, so that a setting is only
+# chosen for a difference that repeats.
+DEFAULT_MARGIN = 0.005
+CONFIRM_TOP = 6     # leaders of the first round that are timed again
+CONFIRM_ROUNDS = 4  # interleaved rounds of the confirming timing
+
+
+def distance(cand: dict, defaults: dict) -> int:
+    """Number of settings in which a candidate differs from the defaults; a
+    single-launch path counts as differing in all of them and one more."""
+    if cand["path"] != "bucketed":
+        return len(TUNING_KEYS) + 1
+    return sum(cand[k] != defaults[k] for k in TUNING_KEYS)
 
 
 def pick(results, defaults: dict, margin: float = DEFAULT_MARGIN):
-    """(seconds, candidate) of the choice among the timed (seconds, candidate)
-    pairs: the fastest, unless the bucketed path with the `defaults` tuning is
-    within `margin` of it; also returns the defaults' time (None if they were
-    not timed)."""
+    """Choice among timed (seconds, candidate) pairs: of the candidates within
+    `margin` of the fastest, the one closest to `defaults`, then the faster.
+    Returns (seconds, candidate, seconds of the defaults or None)."""
     if not results:
         raise ValueError("no timed candidates")
-    best = min(results, key=lambda r: r[0])
-    default = next((r for r in results if r[1]["path"] == "bucketed" and all(
-        r[1][k] == defaults[k] for k in TUNING_KEYS)), None)
-    if default is not None and best[0] >= default[0] * (1.0 - margin):
-        best = default
+    fastest = min(r[0] for r in results)
+    near = [r for r in results if r[0] <= fastest * (1.0 + margin)]
+    best = min(near, key=lambda r: (distance(r[1], defaults), r[0]))
+    default = next((r for r in results if distance(r[1], defaults) == 0), None)
     return best[0], best[1], None if default is None else default[0]
 
 
@@ -114,27 +126,42 @@ def tune(keys, data, offsets, lengths, key_idx=None, width: int = 1, reps: int =
          cache_path: Optional[str] = DEFAULT_CACHE, verbose: bool = False,
          margin: float = DEFAULT_MARGIN) -> dict:
     """Time every candidate on this batch (on a private stream, so that
-    hipGraph capture is possible) and cache the choice of `pick`; returns it."""
+    hipGraph capture is possible), re-time the leaders and the defaults, and
+    cache the choice of `pick` over the second timing; returns it."""
     saved = hh.get_tuning()
     out = torch.empty((offsets.numel(), width), dtype=torch.int64, device=offsets.device)
-    results = []
     stream = torch.cuda.Stream()
+
+    def timed(c):
+        if c["path"] == "bucketed":
+            hh.set_tuning(**dict(saved, **{k: v for k, v in c.items() if k != "path"}))
+        return _time(lambda: hh.hash(keys, data, offsets, lengths, key_idx, width, c["path"],
+                                     out), reps)
+
+    results = []
     try:
         with torch.cuda.stream(stream):
             for c in candidates():
-                if c["path"] == "bucketed":
-                    hh.set_tuning(**dict(saved, **{k: v for k, v in c.items() if k != "path"}))
-                sec = _time(lambda: hh.hash(keys, data, offsets, lengths, key_idx, width,
-                                            c["path"], out), reps)
-                results.append((sec, c))
+                results.append((timed(c), c))
                 if verbose:
-                    print("autotune %.4f ms %s" % (sec * 1e3, c), flush=True)
+                    print("autotune %.4f ms %s" % (results[-1][0] * 1e3, c), flush=True)
+            leaders = [c for _, c in sorted(results, key=lambda r: r[0])[:CONFIRM_TOP]]
+            if not any(distance(c, saved) == 0 for c in leaders):
+                leaders.append(dict({k: saved[k] for k in TUNING_KEYS}, path="bucketed"))
+            total = [0.0] * len(leaders)
+            for _ in range(CONFIRM_ROUNDS):
+                for i, c in enumerate(leaders):
+                    total[i] += timed(c)
+            confirmed = [(t / CONFIRM_ROUNDS, c) for t, c in zip(total, leaders)]
+            if verbose:
+                for t, c in confirmed:
+                    print("confirm %.4f ms %s" % (t * 1e3, c), flush=True)
     finally:
         hh.set_tuning(**saved)
-    sec, best, default = pick(results, saved, margin)
-    fastest = min(r[0] for r in results)
+    sec, best, default = pick(confirmed, saved, margin)
     entry = dict(best, ms=sec * 1e3, default_ms=None if default is None else default * 1e3,
-                 fastest_ms=fastest * 1e3, margin=margin, candidates=len(results))
+                 fastest_ms=min(r[0] for r in confirmed) * 1e3, margin=margin,
+                 candidates=len(results), confirmed=len(confirmed))
     if cache_path:
         cache = _load(cache_path)
         cache[signature(lengths, width)] = entry

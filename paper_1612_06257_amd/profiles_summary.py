@@ -6,6 +6,10 @@
     python -m paper_1612_06257_amd.profiles_summary valu <sq.csv> <workload> <out.json> \
         [<kernel prefix> [<bench.py arguments of the profiled run>]]
 
+`traffic` and `valu` take `--tuning JSON`: the hh_tuning the profiled runs
+were given with `bench.py --tuning`, recorded so that a benchmark reuses the
+figures only for launches made with that tuning.
+
 `traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of
 hh_long_kernel by the factor that makes the same counters read the known size
 of a plain copy kernel, and records the hash of the kernel sources so that a
@@ -41,8 +45,12 @@ def _per_kernel(path):
     return {k: sum(v) / len(v) for k, v in agg.items()}
 
 
+def _tuning_arg(tuning):
+    return "" if tuning is None else " --tuning '%s'" % json.dumps(tuning, sort_keys=True)
+
+
 def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
-            kernel_prefix="hh::hh_long_kernel<1"):
+            kernel_prefix="hh::hh_long_kernel<1", tuning=None):
     sys.path.insert(0, ".")
     import bench
     f = _per_kernel(fetch)
@@ -59,9 +67,12 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
         "fetch_scale": f_factor, "write_scale": w_factor,
         "hbm_bytes_per_launch": f[kernel] * 1024.0 * f_factor + w[kernel] * 1024.0 * w_factor,
         "other_kernels_fetch_kib": {k: v for k, v in f.items() if k != kernel},
+        "tuning": tuning,
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving --no-pipelined",
-            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune --no-serving --no-pipelined",
+            "rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py "
+            + BENCH_ARGS + _tuning_arg(tuning),
+            "rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py "
+            + BENCH_ARGS + _tuning_arg(tuning),
             "rocprofv3 --pmc FETCH_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
             "rocprofv3 --pmc WRITE_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
         ],
@@ -80,7 +91,8 @@ BENCH_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune -
               "--no-pipelined")
 
 
-def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1", bench_args=BENCH_ARGS):
+def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1", bench_args=BENCH_ARGS,
+         tuning=None):
     """Per-dispatch means of the SQ counters of one kernel (one rocprofv3
     --pmc run of bench.py with VALU_COUNTERS), with the kernel-source hash."""
     sys.path.insert(0, ".")
@@ -95,18 +107,26 @@ def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1", bench_args=B
            "source_sha": bench.kernel_source_sha(_base(kernel)),
            "per_launch": {c: sum(v) / len(v) for c, v in sorted(per.items())},
            "launches": len(next(iter(per.values()))),
+           "tuning": tuning,
            "command": "rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " -d <dir> -o bench "
-                      "--output-format csv -- python -u bench.py " + bench_args}
+                      "--output-format csv -- python -u bench.py " + bench_args
+                      + _tuning_arg(tuning)}
     json.dump(rec, open(out, "w"), indent=1)
     open(out, "a").write("\n")
     return rec
 
 
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
-        kernel_stats(sys.argv[2], sys.argv[3], sys.argv[4])
-    elif sys.argv[1] == "valu":
-        print(json.dumps(valu(*sys.argv[2:7]), indent=1))
+    argv = sys.argv[1:]
+    tuning = None
+    if "--tuning" in argv:
+        i = argv.index("--tuning")
+        tuning = json.loads(argv[i + 1])
+        del argv[i:i + 2]
+    if argv[0] == "stats":
+        kernel_stats(argv[1], argv[2], argv[3])
+    elif argv[0] == "valu":
+        print(json.dumps(valu(*argv[1:6], tuning=tuning), indent=1))
     else:
-        print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5],
-                                 int(sys.argv[6]), sys.argv[7], sys.argv[8]), indent=1))
+        print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], int(argv[5]), argv[6],
+                                 argv[7], tuning=tuning), indent=1))

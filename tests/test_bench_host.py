@@ -72,3 +72,29 @@ def test_committed_counter_summaries_are_well_formed(path):
     else:
         assert rec["hbm_bytes_per_launch"] > 0
         assert 0.5 < rec["fetch_scale"] < 4 and 0.5 < rec["write_scale"] < 4
+
+
+def test_tuning_argument_is_checked():
+    assert bench.parse_tuning('{"lane4_min_bytes": 0}') == {"lane4_min_bytes": 0}
+    for bad in ('[]', '{}', '{"ring": 72}', '{"long_ring": "72"}', '{"use_graph": true}', 'x'):
+        with pytest.raises(ValueError):
+            bench.parse_tuning(bad)
+    r = _run("--tuning", '{"ring": 72}')
+    assert r.returncode == 2 and "unknown fields" in r.stderr
+
+
+def test_summaries_apply_only_to_launches_like_theirs():
+    tuning = {"lane4_min_bytes": 0, "waves_per_cu": 4, "use_graph": 0, "long_ring": 72,
+              "isolate_long": 1}
+    rec = {"source_sha": bench.kernel_source_sha("hh_long_kernel"), "workload": "w",
+           "tuning": dict(tuning)}
+    assert bench.profile_applies(rec, "hh_long_kernel", "w", tuning)
+    assert not bench.profile_applies(rec, "hh_long_kernel", "other", tuning)
+    assert not bench.profile_applies(rec, "hh_long_kernel", "w", dict(tuning, long_ring=96))
+    assert not bench.profile_applies(dict(rec, tuning=None), "hh_long_kernel", "w", tuning)
+    assert not bench.profile_applies(dict(rec, source_sha="0" * 16), "hh_long_kernel", "w",
+                                     tuning)
+    assert not bench.profile_applies(None, "hh_long_kernel", "w", tuning)
+    # the single-launch kernels do not read the tuning
+    rec1 = {"source_sha": bench.kernel_source_sha("hh_thread_kernel"), "workload": "w"}
+    assert bench.profile_applies(rec1, "hh_thread_kernel", "w", dict(tuning, long_ring=96))
