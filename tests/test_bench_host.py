@@ -65,6 +65,9 @@ def test_committed_counter_summaries_are_well_formed(path):
     assert name.startswith(base + "_")
     assert len(rec["source_sha"]) == 16
     assert rec["workload"]
+    if base == "hh_long_kernel":
+        # the bucketed kernel's launches depend on the tuning it ran with
+        assert set(rec["tuning"]) == set(bench.TUNING_KEYS)
     if name.endswith("_valu.json"):
         c = rec["per_launch"]
         assert c["SQ_INSTS_VALU"] > 0 and c["SQ_WAVES"] > 0
