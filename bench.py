@@ -38,6 +38,7 @@ import json
 import os
 import sys
 import time
+from typing import Optional
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -72,6 +73,9 @@ PATH_KERNEL = {"auto": "hh_long_kernel", "bucketed": "hh_long_kernel",
 
 
 TUNING_KEYS = ("lane4_min_bytes", "waves_per_cu", "use_graph", "long_ring", "isolate_long")
+# the library's defaults (hh_get_tuning before any hh_set_tuning)
+DEFAULT_TUNING = {"lane4_min_bytes": 128, "waves_per_cu": 4, "use_graph": 0, "long_ring": 72,
+                  "isolate_long": 1}
 
 
 def parse_tuning(text: str) -> dict:
@@ -105,8 +109,30 @@ def profile_applies(rec, kernel: str, workload_name: str, tuning: dict) -> bool:
     return True
 
 
-def profile_file(kernel: str, workload: str, what: str) -> str:
-    return os.path.join(PROFILE_DIR, "%s_%s_%s.json" % (kernel, workload, what))
+def tuning_tag(tuning: Optional[dict]) -> str:
+    """File-name tag of a tuning: its fields that differ from the library
+    defaults, e.g. "_lane4_min_bytes0" (empty for the defaults)."""
+    if not tuning:
+        return ""
+    return "".join("_%s%d" % (k, tuning[k]) for k in TUNING_KEYS
+                   if k in tuning and tuning[k] != DEFAULT_TUNING[k])
+
+
+def profile_file(kernel: str, workload: str, what: str, tuning: Optional[dict] = None) -> str:
+    """Path of a committed counter summary; summaries of the bucketed
+    kernel taken with other than the default tuning carry its tag."""
+    return os.path.join(PROFILE_DIR, "%s_%s%s_%s.json" % (kernel, workload, tuning_tag(tuning),
+                                                          what))
+
+
+def find_profile(kernel: str, workload: str, what: str, workload_name: str, tuning: dict):
+    """The committed summary that describes launches of `kernel` on this
+    workload with this tuning, or None."""
+    for t in ((tuning,) if kernel == "hh_long_kernel" else ()) + (None,):
+        rec = load_json(profile_file(kernel, workload, what, t))
+        if profile_applies(rec, kernel, workload_name, tuning):
+            return rec
+    return None
 
 
 def kernel_source_sha(kernel: str = "hh_long_kernel") -> str:
@@ -381,8 +407,8 @@ def main(argv=None) -> int:
     achieved = kernel_bytes / (kernel_ms_mean * 1e6) if kernel_ms_mean else None
     timed_tuning = hh.get_tuning()
     traffic = None
-    tr = load_json(profile_file(kernel, args.workload, "traffic"))
-    if profile_applies(tr, kernel, b.name, timed_tuning):
+    tr = find_profile(kernel, args.workload, "traffic", b.name, timed_tuning)
+    if tr:
         traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -392,8 +418,8 @@ def main(argv=None) -> int:
     # integer-VALU roof of the same kernel, from its counted VALU instructions
     # (each a wave of 64 lane-ops) over the mean launch time measured above
     valu_roof = None
-    vc = load_json(profile_file(kernel, args.workload, "valu"))
-    if profile_applies(vc, kernel, b.name, timed_tuning) and kernel_ms_mean:
+    vc = find_profile(kernel, args.workload, "valu", b.name, timed_tuning)
+    if vc and kernel_ms_mean:
         c = vc["per_launch"]
         lane_ops = c["SQ_INSTS_VALU"] * 64.0
         valu_roof = {"bound": "alu", "kernel": kernel,

@@ -101,3 +101,19 @@ def test_summaries_apply_only_to_launches_like_theirs():
     # the single-launch kernels do not read the tuning
     rec1 = {"source_sha": bench.kernel_source_sha("hh_thread_kernel"), "workload": "w"}
     assert bench.profile_applies(rec1, "hh_thread_kernel", "w", dict(tuning, long_ring=96))
+
+
+def test_default_tuning_is_the_library_default():
+    from paper_1612_06257_amd import hh
+    assert hh.get_tuning() == bench.DEFAULT_TUNING
+
+
+def test_summary_file_names_carry_non_default_tuning():
+    d = dict(bench.DEFAULT_TUNING)
+    assert bench.profile_file("hh_long_kernel", "lognormal", "traffic", d).endswith(
+        "hh_long_kernel_lognormal_traffic.json")
+    assert bench.profile_file("hh_long_kernel", "lognormal", "valu",
+                              dict(d, lane4_min_bytes=0)).endswith(
+        "hh_long_kernel_lognormal_lane4_min_bytes0_valu.json")
+    assert bench.tuning_tag(dict(d, long_ring=96, lane4_min_bytes=0)) == \
+        "_lane4_min_bytes0_long_ring96"
