@@ -214,7 +214,9 @@ typedef struct {
 void hh_get_tuning(hh_tuning* t);
 hh_status hh_set_tuning(const hh_tuning* t);
 
-/* Free the library's per-device workspaces and cached graphs. */
+/* Free the library's per-device workspaces and cached graphs.  Call it after
+ * synchronising the streams the library was called on, and while no other
+ * host thread is inside a library call; later calls allocate afresh. */
 hh_status hh_release(void);
 
 /* Device address of pinned host memory (hipHostMalloc'd, e.g. a pinned

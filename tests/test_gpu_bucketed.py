@@ -141,6 +141,37 @@ def test_autotune_caches_and_stays_bit_exact(hh, tmp_path):
         hh.set_tuning(**base)
 
 
+def test_calls_after_release_allocate_afresh(hh):
+    # hh_release frees every workspace and cached graph; the next calls, on
+    # the stream used before and on another one, build new ones and hash
+    # exactly, eagerly and as replayed graphs
+    base = hh.get_tuning()
+    keys, key_idx, data, offsets, lengths = _batch(seed=61)
+    want = oracle_ref(1, keys, key_idx, data, offsets, lengths)
+    k, ki, d, o, L = batch_to_device(keys, key_idx, data, offsets, lengths)
+    side = torch.cuda.Stream()
+    try:
+        for use_graph in (0, 1):
+            hh.set_tuning(**dict(base, use_graph=use_graph))
+            for rep in range(2):
+                announce("release", use_graph, rep)
+                with torch.cuda.stream(side):
+                    before = hh.hash(k, d, o, L, ki, 1, "auto")
+                torch.cuda.synchronize()
+                hh.release()
+                with torch.cuda.stream(side):
+                    after_side = hh.hash(k, d, o, L, ki, 1, "auto")
+                after_default = hh.hash(k, d, o, L, ki, 1, "auto")
+                torch.cuda.synchronize()
+                for name, got in (("before", before), ("side", after_side),
+                                  ("default", after_default)):
+                    assert_same(hh.to_u64(got), want, "graph %d rep %d %s" % (use_graph, rep,
+                                                                               name))
+    finally:
+        hh.set_tuning(**base)
+        torch.cuda.synchronize()
+
+
 def test_back_to_back_calls_share_the_plan(hh):
     # consecutive calls on one stream reuse one workspace; each call's last
     # wave leaves the plan zeroed for the next one, so batches of different
