@@ -97,5 +97,13 @@ def test_tuning_roundtrip():
         hh.set_tuning(waves_per_cu=0)
     with pytest.raises(hh.HHError):
         hh.set_tuning(**dict(t, isolate_long=2))
+    for bad in (dict(long_ring=60), dict(long_ring=0), dict(waves_per_cu=33),
+                dict(use_graph=2)):
+        with pytest.raises(hh.HHError):
+            hh.set_tuning(**dict(t, **bad))
+        assert hh.get_tuning() == t  # a rejected setting changes nothing
+    for ring in (36, 48, 72, 96):
+        hh.set_tuning(**dict(t, long_ring=ring))
+        assert hh.get_tuning()["long_ring"] == ring
     hh.set_tuning(**t)
     assert hh.get_tuning() == t
