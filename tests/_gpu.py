@@ -24,7 +24,10 @@ def announce(*what):
 
 
 def dev(a, dtype=None):
-    t = torch.from_numpy(np.ascontiguousarray(a))
+    a = np.ascontiguousarray(a)
+    if not a.flags.writeable:  # e.g. np.frombuffer over bytes; torch wants writable memory
+        a = a.copy()
+    t = torch.from_numpy(a)
     if dtype is not None:
         t = t.view(dtype)
     return t.cuda()
