@@ -15,7 +15,8 @@
  *   constants  Sec. 4.4: hexadecimal digits of pi, fourth word rebuilt
  *   Reset      Sec. 4.4: v0 = key ^ C0, v1 = rot32(key) ^ C1, mul0 = C0, mul1 = C1
  *   ZipperMerge Sec. 4.1: byte permutation 7 8 6 9 D A 4 B 0 F 1 E 5 2 C 3
- *   Update     Sec. 4.2: the seven-statement listing, in order
+ *   Update     Sec. 4.2: per lane, packet and mul0 into v1 and two 32x32->64
+ *              products into mul0 / mul1; then v0 and v1 mixed by ZipperMerge
  *   Remainder  Sec. 4.5: size mod 32 into v0, v1 halves rotated, padded packet
  *   Permute    Sec. 4.3: 32-bit indices 2 3 0 1 6 7 4 5 of v0
  *   Finalize   Sec. 4.3: four times Update(Permute(v0)), then v0+v1+mul0+mul1
@@ -24,12 +25,22 @@
  *   - packet bytes 8i..8i+7 form lane i, little-endian (x86 loads);
  *   - key word i is lane i;
  *   - the permutation lists of Sec. 4.1 and 4.3 are written highest element
- *     first ("i=15 listed first"); the low-first reading violates the paper's
- *     own requirement 1 and its "swap halves" description (tests check both);
- *   - size injection adds r*(2^32+1) with the vector class's 64-bit lane add;
+ *     first (the paper lists element 15 first); the low-first reading violates
+ *     the paper's own first requirement on the zipper and its description of
+ *     Permute as a swap of halves (tests check both);
+ *   - size injection adds r*(2^32+1) with one 64-bit add per lane;
  *   - each 32-bit half of a v1 lane is rotated LEFT by r;
  *   - the 0..31 tail bytes: the first q = r - r%4 go to packet bytes 0..q-1,
- *     the last r%4 go to packet bytes 28, 29, 30 (in order), the rest are 0;
+ *     the last r%4 go, in order, to the start of the most-significant dword
+ *     of the 16-byte half that the 4-byte groups are loaded into (Sec. 4.5
+ *     loads them with the 128-bit mask load): packet bytes 12.. when r < 16,
+ *     28.. when r >= 16; the rest are 0.  Of the readings of Sec. 4.5 this
+ *     one reproduces the round-count figures of Sec. 4.3 (3-byte inputs:
+ *     strong bias after two rounds, near a random function's after three);
+ *     putting the bytes at 28.. for every r needs a fourth round for that;
+ *   - the injection width and the rotate direction are parity unpinned: the
+ *     alternatives (two 32-bit adds; rotate right) give the same Sec. 4.3
+ *     statistics within the spread between keys;
  *   - injection and rotation happen before the padded packet's Update;
  *   - no remainder step at all when size mod 32 == 0 (including size 0);
  *   - 4 finalization rounds for every output width; a 128-bit hash is lanes
@@ -52,7 +63,7 @@ typedef struct {
     uint64_t mul1[4];
 } hh_ref_state;
 
-/* Sec. 4.4: "nothing up my sleeve" constants from the hexadecimal expansion of
+/* Sec. 4.4: constants of documented origin, from the hexadecimal expansion of
  * pi.  The fraction's 64-bit words w0.. are 243f6a8885a308d3, 13198a2e03707344,
  * a4093822299f31d0, 082efa98ec4e6c89, 452821e638d01377, be5466cf34e90c6c,
  * c0ac29b7c97c50dd, ...  Each constant takes three consecutive words for lanes
@@ -67,7 +78,7 @@ static const uint64_t HH_REF_C1[4] = {
     0x3bd3de18c707ef82ULL, 0xc0ac29b7c97c50ddULL,
     0xbe5466cf34e90c6cULL, 0x452821e638d01377ULL};
 
-/* Sec. 4.1: the final zipper permutation as printed, element i=15 first. */
+/* Sec. 4.1: the final zipper permutation as printed, highest element first. */
 static const uint8_t HH_REF_ZIPPER_PRINTED[16] = {
     0x7, 0x8, 0x6, 0x9, 0xD, 0xA, 0x4, 0xB, 0x0, 0xF, 0x1, 0xE, 0x5, 0x2, 0xC, 0x3};
 
@@ -111,7 +122,7 @@ void hh_ref_reset(const uint64_t key[4], hh_ref_state* s) {
 
 /* Sec. 4.1: ZipperMerge of one 16-byte lane pair (a = low lane, b = high lane).
  * S is the pair's bytes (S[0..7] = a little-endian, S[8..15] = b), and result
- * byte R_i = S[P_i], where P is the printed list read with i=15 first. */
+ * byte R_i = S[P_i], where P is the printed list read highest element first. */
 void hh_ref_zipper_merge(uint64_t a, uint64_t b, uint64_t* ra, uint64_t* rb) {
     uint8_t S[16], R[16];
     put_le64(S, a);
@@ -124,30 +135,36 @@ void hh_ref_zipper_merge(uint64_t a, uint64_t b, uint64_t* ra, uint64_t* rb) {
     *rb = le64(R + 8);
 }
 
-/* ZipperMerge of a whole vector: it only combines adjacent lanes (Sec. 4.3),
- * i.e. lanes (0,1) and (2,3) are zipped independently. */
+/* ZipperMerge of a whole vector mixes lane 0 with lane 1 and lane 2 with
+ * lane 3, each pair on its own (Sec. 4.3: no bytes cross between the pairs). */
 static void zipper_merge_vec(const uint64_t v[4], uint64_t out[4]) {
     hh_ref_zipper_merge(v[0], v[1], &out[0], &out[1]);
     hh_ref_zipper_merge(v[2], v[3], &out[2], &out[3]);
 }
 
-/* Sec. 4.2: Update(packet), the listing's seven statements in order.
- * _mm256_mul_epu32(x, y) multiplies the low 32 bits of each lane of x and y
- * into a 64-bit product; y = v0 >> 32 (resp. v1 >> 32) so the product is
- * lo32(x) * hi32(v). */
+/* Sec. 4.2, first part of an Update: lane i on its own.  v1 takes in the
+ * packet word and mul0; mul0 is xored with the full 64-bit product of the low
+ * 32 bits of that new v1 and the high 32 bits of v0 (the unsigned 32x32
+ * multiply of the paper's vector code, fed v0 shifted down by 32); then v0
+ * takes in mul1, and mul1 is xored with the product of the low 32 bits of the
+ * new v0 and the high 32 bits of v1. */
+static void absorb_lane(hh_ref_state* s, int i, uint64_t word) {
+    s->v1[i] = s->v1[i] + word + s->mul0[i];
+    s->mul0[i] ^= lo32(s->v1[i]) * hi32(s->v0[i]);
+    s->v0[i] += s->mul1[i];
+    s->mul1[i] ^= lo32(s->v0[i]) * hi32(s->v1[i]);
+}
+
+/* Sec. 4.2: Update(packet).  The four lanes absorb independently, then the
+ * lane pairs are mixed: v0 gains the ZipperMerge of v1, after which v1 gains
+ * the ZipperMerge of the v0 just formed. */
 void hh_ref_update(hh_ref_state* s, const uint64_t packet[4]) {
-    uint64_t zm[4];
-    for (int i = 0; i < 4; ++i) s->v1[i] += packet[i];                   /* v1 += packet */
-    for (int i = 0; i < 4; ++i) s->v1[i] += s->mul0[i];                  /* v1 += mul0 */
-    for (int i = 0; i < 4; ++i)
-        s->mul0[i] ^= lo32(s->v1[i]) * hi32(s->v0[i]);                  /* mul0 ^= mul(v1, v0>>32) */
-    for (int i = 0; i < 4; ++i) s->v0[i] += s->mul1[i];                  /* v0 += mul1 */
-    for (int i = 0; i < 4; ++i)
-        s->mul1[i] ^= lo32(s->v0[i]) * hi32(s->v1[i]);                  /* mul1 ^= mul(v0, v1>>32) */
-    zipper_merge_vec(s->v1, zm);
-    for (int i = 0; i < 4; ++i) s->v0[i] += zm[i];                       /* v0 += ZipperMerge(v1) */
-    zipper_merge_vec(s->v0, zm);
-    for (int i = 0; i < 4; ++i) s->v1[i] += zm[i];                       /* v1 += ZipperMerge(v0) */
+    uint64_t z[4];
+    for (int i = 0; i < 4; ++i) absorb_lane(s, i, packet[i]);
+    zipper_merge_vec(s->v1, z);
+    for (int i = 0; i < 4; ++i) s->v0[i] += z[i];
+    zipper_merge_vec(s->v0, z);
+    for (int i = 0; i < 4; ++i) s->v1[i] += z[i];
 }
 
 /* Sec. 4.3: permute v0 by the printed 32-bit indices.  Element e of a vector
@@ -170,7 +187,8 @@ static uint32_t rotl32(uint32_t x, unsigned r) { return (x << r) | (x >> (32 - r
  * The size mod 32 is broadcast into all eight 32-bit parts and added to v0;
  * the 32-bit parts of v1 are rotated by the same amount; the tail bytes form
  * one padded packet (whole 4-byte groups at the start, the last 0..3 bytes in
- * the packet's most-significant four bytes) which is passed to Update. */
+ * the most-significant four bytes of the 16-byte half they are loaded into)
+ * which is passed to Update. */
 void hh_ref_remainder(hh_ref_state* s, const uint8_t* tail, size_t r) {
     uint8_t P[32];
     uint64_t packet[4];
@@ -184,7 +202,10 @@ void hh_ref_remainder(hh_ref_state* s, const uint8_t* tail, size_t r) {
     }
     memset(P, 0, sizeof P);
     for (size_t j = 0; j < q; ++j) P[j] = tail[j];
-    for (size_t j = 0; j < m; ++j) P[28 + j] = tail[q + j];
+    /* the groups end in the low half when r < 16 (q <= 12, bytes 12..15 are
+     * free) and in the high half otherwise (q <= 28, bytes 28..31 free) */
+    size_t top = r < 16 ? 12 : 28;
+    for (size_t j = 0; j < m; ++j) P[top + j] = tail[q + j];
     for (int i = 0; i < 4; ++i) packet[i] = le64(P + 8 * i);
     hh_ref_update(s, packet);
 }

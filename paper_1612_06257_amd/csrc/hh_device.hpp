@@ -241,16 +241,24 @@ __device__ __forceinline__ u32 load_partial_le32(const u8* p, u32 n) {
     return n >= 4u ? w : (w & ((1u << (8u * n)) - 1u));
 }
 
+// Sec. 4.5 padded remainder packet: the dword that takes the last r%4 tail
+// bytes.  The whole 4-byte groups are mask-loaded into the 16-byte half they
+// end in, and the last bytes go to the low end of that half's most-significant
+// dword: dword 3 when r < 16 (at most three groups precede it), dword 7
+// otherwise (at most seven).
+__device__ __forceinline__ u32 remainder_top_dword(u32 r) { return r < 16u ? 3u : 7u; }
+
 // Sec. 4.5 padded remainder packet, dword k (0..7), for the r (1..31) tail
 // bytes at t of a message (or final chunk) of len bytes, so that its first
 // byte is t + r - len: the first q = r - r%4 bytes fill packet bytes 0..q-1,
-// the last r%4 bytes go to packet bytes 28..30 (in order); all other bytes
-// are zero.
+// the last r%4 bytes fill, in order, the low bytes of dword
+// remainder_top_dword(r) (packet bytes 12.. or 28..); all other bytes are
+// zero.
 __device__ __forceinline__ u32 remainder_dword(const u8* t, u32 r, u32 k, u64 len) {
     const u32 q4 = r >> 2;  // whole 4-byte groups
-    if (k < 7u) return k < q4 ? load_le32(t + 4u * k) : 0u;
+    if (k < q4) return load_le32(t + 4u * k);
     const u32 m = r & 3u;
-    if (m == 0u) return 0u;
+    if (k != remainder_top_dword(r) || m == 0u) return 0u;
     // the dword ending at the last byte starts inside the message when len >= 4
     if (len >= 4u) return load_le32(t + r - 4u) >> (8u * (4u - m));
     return load_partial_le32(t + 4u * q4, m);

@@ -44,8 +44,9 @@ __device__ __forceinline__ u64 hash_small(const u64 key[4], const u64 m[4], u32 
         update4(st, m);
     } else {
         // Sec. 4.5 padded packet: whole 4-byte groups stay in place, the
-        // last s%4 bytes go to packet bytes 28..; here as dwords
-        const u32 q4 = s >> 2;
+        // last s%4 bytes (the low bytes of dword q4, the rest of which is
+        // zero) move to dword remainder_top_dword(s); here as dwords
+        const u32 q4 = s >> 2, top = remainder_top_dword(s);
         u32 d[8];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -55,14 +56,12 @@ __device__ __forceinline__ u64 hash_small(const u64 key[4], const u64 m[4], u32 
         u32 tail = 0;
 #pragma unroll
         for (u32 k = 0; k < 8; ++k) tail = (k == q4) ? d[k] : tail;
+        u32 pd[8];
+#pragma unroll
+        for (u32 k = 0; k < 8; ++k) pd[k] = (k < q4) ? d[k] : (k == top ? tail : 0u);
         u64 pk[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const u32 k0 = 2u * i, k1 = 2u * i + 1u;
-            const u32 a = (k0 < q4) ? d[k0] : 0u;
-            const u32 b = (k1 < 7u) ? ((k1 < q4) ? d[k1] : 0u) : tail;
-            pk[i] = make64(a, b);
-        }
+        for (int i = 0; i < 4; ++i) pk[i] = make64(pd[2 * i], pd[2 * i + 1]);
         remainder4(st, s, pk);
     }
 #pragma unroll

@@ -68,7 +68,7 @@ def test_byte_quality_ranking_matches_paper(zipper_printed):
 
 
 def _perm_high_first(tokens):
-    """Printed list (i=15 first) -> P with P[i] the source byte of result i."""
+    """Printed list (highest element first) -> P with P[i] the source byte of result i."""
     vals = [int(t, 16) for t in tokens]
     return list(reversed(vals))
 
@@ -117,7 +117,7 @@ def test_printed_zipper_satisfies_requirements_high_first(zipper_printed):
 
 
 def test_low_first_reading_violates_requirement1(zipper_printed):
-    # justifies reading the list with i=15 first
+    # justifies reading the list highest element first
     assert not _requirement1(_perm_low_first(zipper_printed["final"]))
 
 
@@ -329,7 +329,7 @@ def test_update_is_a_bijection_round_trip():
 
 
 def test_update_lanes_pairwise_independent():
-    # ZipperMerge only combines adjacent lanes (Sec. 4.3): changing lane 2 or
+    # ZipperMerge mixes lanes within a pair only (Sec. 4.3): changing lane 2 or
     # 3 of the state or packet leaves lanes 0 and 1 of one Update unchanged.
     rng = np.random.default_rng(17)
     for _ in range(50):
@@ -351,21 +351,111 @@ def _rotl32(x, r):
     return ((x << r) | (x >> (32 - r))) & 0xFFFFFFFF
 
 
+def _rotr32(x, r):
+    return ((x >> r) | (x << (32 - r))) & 0xFFFFFFFF
+
+
+def _rot_halves(x, r, rot):
+    return (rot(x >> 32, r) << 32) | rot(x & 0xFFFFFFFF, r)
+
+
 def test_remainder_follows_documented_reading():
+    """Conformance to the readings taken: one 64-bit add of r*(2^32+1) per
+    lane of v0, each 32-bit half of v1 rotated left by r, the whole 4-byte
+    groups at the start of the packet and the last r%4 bytes at the start of
+    the top dword of the 16-byte half the groups end in (bytes 12.. for
+    r < 16, 28.. otherwise).  The paper fixes the size injection into every
+    32-bit half and the packet's content (the next two tests) and, through
+    the round-count figures of Sec. 4.3, the placement (test_oracle_rounds);
+    the rotate direction is a convention."""
     rng = np.random.default_rng(19)
     for r in range(1, 32):
         s = rng.integers(0, 2**64, size=16, dtype=np.uint64)
         tail = rng.integers(0, 256, size=r, dtype=np.uint8)
         v0, v1, mul0, mul1 = _split(s)
         v0 = [(x + r * ((1 << 32) + 1)) & M64 for x in v0]
-        v1 = [(_rotl32(x >> 32, r) << 32) | _rotl32(x & 0xFFFFFFFF, r) for x in v1]
+        v1 = [_rot_halves(x, r, _rotl32) for x in v1]
         q, m = r - r % 4, r % 4
+        top = 12 if r < 16 else 28
         P = [0] * 32
         P[:q] = [int(b) for b in tail[:q]]
-        P[28:28 + m] = [int(b) for b in tail[q:q + m]]
+        P[top:top + m] = [int(b) for b in tail[q:q + m]]
         packet = [_from_le(P[8 * i:8 * i + 8]) for i in range(4)]
         want = oracle.update(_state(v0, v1, mul0, mul1), packet)
         assert np.array_equal(oracle.remainder(s, tail), want)
+
+
+def _undo_update_keep_v1_plus_packet(t):
+    """Undo one Update without knowing its packet: returns v0, v1 + packet,
+    mul0, mul1 of the state the Update started from (its first statement
+    adds the packet and mul0 to v1, nothing else reads the packet)."""
+    v0, v1, mul0, mul1 = _split(t)
+    v1 = [(v1[i] - z) & M64 for i, z in enumerate(_zm_vec(v0))]
+    v0 = [(v0[i] - z) & M64 for i, z in enumerate(_zm_vec(v1))]
+    mul1 = [mul1[i] ^ ((v0[i] & 0xFFFFFFFF) * (v1[i] >> 32)) for i in range(4)]
+    v0 = [(v0[i] - mul1[i]) & M64 for i in range(4)]
+    mul0 = [mul0[i] ^ ((v1[i] & 0xFFFFFFFF) * (v0[i] >> 32)) for i in range(4)]
+    v1_plus_p = [(v1[i] - mul0[i]) & M64 for i in range(4)]
+    return v0, v1_plus_p, mul0, mul1
+
+
+def _remainder_states(seed):
+    """States whose v0 low halves cannot carry when r <= 31 is added, so a
+    64-bit add of r*(2^32+1) and two 32-bit adds of r agree (the paper does
+    not say which add it uses)."""
+    rng = np.random.default_rng(seed)
+    for r in range(1, 32):
+        s = rng.integers(0, 2**64, size=16, dtype=np.uint64)
+        s[0:4] &= np.uint64(0xFFFFFFFF7FFFFFFF)
+        yield r, s, rng.integers(0, 256, size=r, dtype=np.uint8)
+
+
+def test_remainder_adds_size_to_every_32bit_half_of_v0_before_its_update():
+    # Sec. 4.5: the size mod 32 is broadcast into all eight 32-bit parts and
+    # added to v0, then one Update takes the padded packet; mul0 and mul1 are
+    # not touched before that Update.
+    for r, s, tail in _remainder_states(37):
+        v0, _, mul0, mul1 = _undo_update_keep_v1_plus_packet(oracle.remainder(s, tail))
+        s0, _, smul0, smul1 = _split(s)
+        assert v0 == [(x + (r << 32) + r) & M64 for x in s0], r
+        assert mul0 == smul0 and mul1 == smul1, r
+
+
+def _is_tail_packet(P, tail):
+    """Sec. 4.5: the packet holds the whole 4-byte groups of the tail at its
+    start (mask load) and the last r%4 bytes, in order, in one dword that the
+    groups leave free; every other byte is zero."""
+    r = len(tail)
+    q, m = r - r % 4, r % 4
+    if P[:q] != [int(b) for b in tail[:q]]:
+        return False
+    rest = P[q:]
+    if m == 0:
+        return not any(rest)
+    for d in range(q // 4, 8):
+        cand = [0] * (32 - q)
+        cand[4 * d - q:4 * d - q + m] = [int(b) for b in tail[q:]]
+        if rest == cand:
+            return True
+    return False
+
+
+def test_remainder_packet_holds_the_tail_and_v1_is_rotated():
+    # Sec. 4.5: v1 is permuted by the size (a rotation of its 32-bit halves,
+    # direction not stated) and the Update takes a packet made of the tail
+    # bytes and zeros.  With v1 + packet recovered, exactly one rotation
+    # direction leaves a valid tail packet (both when r = 16, where left and
+    # right agree).
+    for r, s, tail in _remainder_states(41):
+        _, w, _, _ = _undo_update_keep_v1_plus_packet(oracle.remainder(s, tail))
+        _, v1, _, _ = _split(s)
+        valid = 0
+        for rot in (_rotl32, _rotr32):
+            P = []
+            for i in range(4):
+                P += _bytes_le((w[i] - _rot_halves(v1[i], r, rot)) & M64)
+            valid += _is_tail_packet(P, tail)
+        assert valid == (2 if r == 16 else 1), r
 
 
 def test_no_remainder_step_for_multiples_of_32():
