@@ -12,7 +12,9 @@
   truly random function with the same number of cells and samples (drawn
   from binomial counts), the floor any good hash sits on.
 * rounds (Sec. 4.3): all 2^24 three-byte inputs under one key, 1..4
-  finalization rounds, max and mean bias per round count.
+  finalization rounds, max and mean bias per round count.  Each input and its
+  flipped partner are both enumerated, so a cell's flip rate rests on 2^23
+  distinct pairs; a random function's mean bias is sqrt(2/pi)/sqrt(2^23).
 
 Inputs come from SplitMix64 (any strong generator stands in for the paper's
 pcg64_k32; the kernel and the host implement it separately).
@@ -70,7 +72,7 @@ def rounds_study(key=(0x0123456789ABCDEF, 0xFEDCBA9876543210, 0x0F1E2D3C4B5A6978
         mx, mean = bias_of(c, n)
         rec = {"study": "rounds", "msg_bytes": msg_bytes, "inputs": n, "rounds": r,
                "max_bias_pct": 100 * mx, "mean_bias_pct": 100 * mean,
-               "null_mean_bias_pct": 100 * float(np.sqrt(2 / np.pi) / np.sqrt(n)),
+               "null_mean_bias_pct": 100 * float(np.sqrt(2 / np.pi) / np.sqrt(n // 2)),
                "seconds": time.perf_counter() - t0}
         print(json.dumps(rec), flush=True)
         out.append(rec)
