@@ -98,6 +98,33 @@ hh_status hh_hash_path(hh_path path, uint32_t width_words, const uint64_t* keys,
                        uint64_t data_bytes, const uint64_t* offsets, const uint64_t* lengths,
                        uint64_t n_msgs, uint64_t* out, void* stream);
 
+/* Allocation-free batched hashing, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, argument checks and results as
+ * hh_hash_path(HH_PATH_BUCKETED, ...), but the length planner's plan and
+ * index lists live in one fixed array of device memory per GPU, part of the
+ * library's code object (HH_NOALLOC_SCRATCH_BYTES, about 8 MiB, held by every
+ * GPU the library runs on until the process ends), instead of a workspace
+ * the library allocates.  The call allocates nothing (no hipMalloc, no
+ * graph), launches its kernels directly on `stream` and is not seen by the
+ * measurement hook.  Its first call on a device looks up that device's copy
+ * of the array (no allocation); later calls only enqueue kernels.
+ *   - n_msgs above HH_NOALLOC_MAX_MSGS gives HH_ERR_INVALID_ARG (split larger
+ *     batches over several calls on one stream).
+ *   - Each call clears the part of the array that must start at zero, so it
+ *     does not depend on what the previous call left there.
+ *   - Every call on one GPU uses that GPU's one array: calls whose work
+ *     overlaps in time on the same GPU (other streams, other host threads)
+ *     race on it and give wrong results.  The caller orders them (one
+ *     stream, or events between streams).  Calls of the other entry points
+ *     do not touch the array. */
+#define HH_NOALLOC_MAX_MSGS (1u << 20)
+#define HH_NOALLOC_SCRATCH_BYTES (256u * 9u + 8u * HH_NOALLOC_MAX_MSGS)
+hh_status hh_hash_noalloc(uint32_t width_words, const uint64_t* keys, uint32_t n_keys,
+                          const uint32_t* key_idx, const uint8_t* data, uint64_t data_bytes,
+                          const uint64_t* offsets, const uint64_t* lengths, uint64_t n_msgs,
+                          uint64_t* out, void* stream);
+
 /* The "plain" kernel: every message has the same `length`, one thread per
  * message, one launch.  Hashing a batch of mixed lengths with it takes one
  * call per distinct length (the baseline the batched path is measured

@@ -103,6 +103,19 @@ hh_status hh_hash_path(hh_path path, uint32_t width_words, const uint64_t* keys,
     return hh::hash_dispatch(path, a, stream);
 }
 
+hh_status hh_hash_noalloc(uint32_t width_words, const uint64_t* keys, uint32_t n_keys,
+                          const uint32_t* key_idx, const uint8_t* data, uint64_t data_bytes,
+                          const uint64_t* offsets, const uint64_t* lengths, uint64_t n_msgs,
+                          uint64_t* out, void* stream) {
+    const HashArgs a{keys, n_keys, key_idx, data, data_bytes, offsets, lengths, n_msgs, out,
+                     width_words};
+    hh_status s = hh::check_hash_args(a);
+    if (s != HH_OK || a.n == 0) return s;
+    if (a.n > HH_NOALLOC_MAX_MSGS) return HH_ERR_INVALID_ARG;
+    if ((s = hh::check_device(nullptr)) != HH_OK) return s;
+    return hh::launch_bucketed_noalloc(a, (hipStream_t)stream);
+}
+
 hh_status hh_hash64(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,
                     const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
                     const uint64_t* lengths, uint64_t n_msgs, uint64_t* out, void* stream) {

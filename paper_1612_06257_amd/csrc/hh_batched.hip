@@ -587,6 +587,78 @@ hh_status launch_bucketed_w(const HashArgs& a, hipStream_t st, Workspace* ws, co
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free variant (hh_hash_noalloc): the plan and the two index lists
+// of at most HH_NOALLOC_MAX_MSGS messages live in `scratch`, a fixed array in
+// the library's code object.  Every GPU holds its own copy at its own address;
+// host code reaches it only through the address looked up per device below
+// (the array's name on the host is a stand-in, not a device address).
+
+constexpr u64 kNoallocPlanBytes = (sizeof(Plan) + 255) / 256 * 256;
+constexpr u64 kNoallocListBytes = 4ull * HH_NOALLOC_MAX_MSGS;
+constexpr u64 kNoallocScratchBytes = kNoallocPlanBytes + 2 * kNoallocListBytes;
+static_assert(kNoallocScratchBytes == HH_NOALLOC_SCRATCH_BYTES, "hh.h states the array's size");
+
+}  // namespace hh
+
+static __device__ __align__(256) unsigned char scratch[hh::kNoallocScratchBytes];
+
+namespace hh {
+
+namespace {
+
+constexpr int kNoallocDevices = 64;
+std::mutex g_scratch_mutex;
+u8* g_scratch_ptr[kNoallocDevices];  // device address of `scratch` per GPU
+
+// device address of this GPU's `scratch` (dev must be the current device);
+// looked up on the first call on each device, no allocation
+hh_status scratch_address(int dev, u8** out) {
+    if (dev < 0 || dev >= kNoallocDevices) return HH_ERR_UNSUPPORTED_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return HH_ERR_LAUNCH;
+        }
+        g_scratch_ptr[dev] = (u8*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HH_OK;
+}
+
+}  // namespace
+
+hh_status launch_bucketed_noalloc(const HashArgs& a, hipStream_t st) {
+    if (a.n > HH_NOALLOC_MAX_MSGS) return HH_ERR_INVALID_ARG;
+    int dev = 0;
+    hh_status s = check_device(&dev);
+    if (s != HH_OK) return s;
+    u8* base = nullptr;
+    if ((s = scratch_address(dev, &base)) != HH_OK) return s;
+    Workspace ws{dev,
+                 st,
+                 base,
+                 HH_NOALLOC_MAX_MSGS,
+                 (Plan*)base,
+                 (u32*)(base + kNoallocPlanBytes),
+                 (u32*)(base + kNoallocPlanBytes + kNoallocListBytes),
+                 false};
+    const DeviceInfo di = device_info(dev);
+    const hh_tuning tun = current_tuning();
+    const LaunchShape ls = launch_shape(a, di, tun);
+    // the array keeps whatever the last call on this GPU left: clear the plan
+    // with a kernel (the lists are written before they are read)
+    hipLaunchKernelGGL(hh_plan_reset_kernel, dim3(1), dim3(256), 0, st, ws.plan);
+    switch (a.width) {
+        case 1: enqueue_sequence<1>(a, st, &ws, ls, tun, nullptr); break;
+        case 2: enqueue_sequence<2>(a, st, &ws, ls, tun, nullptr); break;
+        default: enqueue_sequence<4>(a, st, &ws, ls, tun, nullptr); break;
+    }
+    return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
+}
+
 // Messages are processed in chunks of at most 2^30 so that indices fit 32 bits.
 hh_status launch_bucketed(const HashArgs& a, hipStream_t st) {
     int dev = 0;

@@ -24,6 +24,7 @@ struct HashArgs {
 hh_status launch_thread(const HashArgs& a, uint64_t uniform_length, hipStream_t st);
 hh_status launch_quad(const HashArgs& a, hipStream_t st);
 hh_status launch_bucketed(const HashArgs& a, hipStream_t st);
+hh_status launch_bucketed_noalloc(const HashArgs& a, hipStream_t st);
 hh_status launch_prf(uint32_t width, const uint64_t* keys, uint32_t n_keys, uint64_t counter_base,
                      uint64_t n, uint64_t* out, hipStream_t st);
 hh_status launch_state_init(const uint64_t* keys, uint32_t n_keys, const uint32_t* key_idx,

@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).restype = ctypes.c_int
         L.hh_hash_path.argtypes = [ctypes.c_int, _u32] + hash_args
         L.hh_hash_path.restype = ctypes.c_int
+        L.hh_hash_noalloc.argtypes = [_u32] + hash_args
+        L.hh_hash_noalloc.restype = ctypes.c_int
         L.hh_hash64_uniform.argtypes = [_vp, _u32, _vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp]
         L.hh_hash64_uniform.restype = ctypes.c_int
         L.hh_prf.argtypes = [_u32, _vp, _u32, _u64, _u64, _vp, _vp]
@@ -166,6 +168,32 @@ def hash(keys: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor, lengths:
     _check(lib().hh_hash_path(PATHS[path], width, _ptr(keys), keys.shape[0], _ptr(key_idx),
                               _ptr(data), data.numel(), _ptr(offsets), _ptr(lengths), n,
                               _ptr(out), _stream()))
+    return out
+
+
+# most messages per hh_hash_noalloc call (HH_NOALLOC_MAX_MSGS in hh.h)
+NOALLOC_MAX_MSGS = 1 << 20
+
+
+def hash_noalloc(keys: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor,
+                 lengths: torch.Tensor, key_idx: Optional[torch.Tensor] = None, width: int = 1,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """hh_hash_noalloc: the bucketed path with the planner's lists in the
+    library's fixed per-GPU array, for at most NOALLOC_MAX_MSGS messages.
+    Pass `out` to keep the call free of allocations (torch's included)."""
+    if width not in (1, 2, 4):
+        raise ValueError("width must be 1, 2 or 4 words")
+    _msg_args(keys, data, offsets, lengths, key_idx)
+    n = offsets.numel()
+    if out is None:
+        out = torch.empty((n, width), dtype=torch.int64, device=offsets.device)
+    else:
+        _dev(out, "out", _W64, 2)
+        if tuple(out.shape) != (n, width):
+            raise ValueError("out must have shape (n, width)")
+    _check(lib().hh_hash_noalloc(width, _ptr(keys), keys.shape[0], _ptr(key_idx), _ptr(data),
+                                 data.numel(), _ptr(offsets), _ptr(lengths), n, _ptr(out),
+                                 _stream()))
     return out
 
 

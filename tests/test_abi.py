@@ -69,6 +69,15 @@ def test_invalid_arguments_rejected_without_device():
     assert L.hh_copy_segments(None, 0, None, 0, None, None, None, 0, 0, None) == 0
     assert L.hh_copy_segments(None, 8, dummy, 8, dummy, dummy, dummy, 1, 8, None) == 1
     assert L.hh_copy_segments(dummy, 8, dummy, 8, dummy, None, dummy, 1, 8, None) == 1
+    # the allocation-free entry point: the same checks, plus its size limit
+    # (HH_NOALLOC_MAX_MSGS = 2^20 messages per call)
+    assert L.hh_hash_noalloc(1, None, 0, None, None, 0, None, None, 0, None, None) == 0
+    assert L.hh_hash_noalloc(3, dummy, 1, None, dummy, 8, dummy, dummy, 3, dummy, None) == 1
+    assert L.hh_hash_noalloc(1, dummy, 0, None, dummy, 8, dummy, dummy, 3, dummy, None) == 1
+    assert L.hh_hash_noalloc(1, dummy, 1, None, dummy, 8, dummy, dummy, 3, None, None) == 1
+    assert L.hh_hash_noalloc(1, dummy, 1, None, dummy, 8, dummy, dummy, (1 << 20) + 1, dummy,
+                             None) == 1
+    assert _hh().NOALLOC_MAX_MSGS == 1 << 20
 
 
 def test_no_device_reported_as_unsupported():
@@ -79,6 +88,8 @@ def test_no_device_reported_as_unsupported():
     vp = ctypes.c_void_p
     dummy = vp(16)
     assert L.hh_hash64(dummy, 1, None, dummy, 8, dummy, dummy, 3, dummy, None) == 2
+    assert L.hh_hash_noalloc(1, dummy, 1, None, dummy, 8, dummy, dummy, 1 << 20, dummy,
+                             None) == 2
 
 
 def test_library_constants_follow_pi_derivation():
