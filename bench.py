@@ -1,7 +1,7 @@
 """Benchmark: batched HighwayHash-64 on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lognormal]
-                    [--path auto|bucketed|lane1|lane4|prf]
+                    [--path auto|bucketed|lane1|lane4|prf] [--width 1|2|4]
 
 One step = one hh_hash64 call over the whole batch (planner + every hash: key
 setup, packets, remainder, finalization, output), inputs already resident in
@@ -18,7 +18,12 @@ Printed as one JSON line:
                batched path, else the path's one kernel): algorithmic bytes
                per launch / its mean duration, timed with HIP events around
                each launch on the launch stream; valu_roofline the same
-               kernel's counted VALU lane-ops over that duration
+               kernel's counted VALU lane-ops over that duration.
+               roofline.bound names the roof that binds: "critical_path"
+               when the longest message's chain covers at least 0.8 of the
+               kernel's time, else "alu" when the VALU fraction exceeds the
+               HBM fraction, else "hbm"; bound_frac is that roof's fraction
+               (achieved/peak/frac/traffic stay the HBM figures)
   critical_path  the longest message's serial Update chain at the measured
                single-wave Update time
   pipelined    the same steps issued round-robin on 2 and 3 streams (each
@@ -27,8 +32,12 @@ Printed as one JSON line:
                batch's few longest chains leave idle; every output is checked
                against the single-stream result
   cpu_baseline the CPU oracle on the host's cores, same batch
-  serving      the serving loop on a 2000-request trace: saturation and 50%
-               load, GB/s and p50/p99 request latency (--no-serving skips it)
+  serving      the serving loop on a 10,000-request trace (power-law lengths
+               on [8 B, 16 MiB], 64 keys, widths 1/2/4, 32 GiB budget):
+               saturation, then Poisson loads at 25/50/80% of the saturation
+               request rate, GB/s and p50/p99 request latency; every result
+               of every point is checked against the oracle in the CPU
+               baseline leg (serving.parity).  --no-serving skips it.
 """
 from __future__ import annotations
 
@@ -46,7 +55,10 @@ if ROOT not in sys.path:
 
 METRIC = "GB/s hashed (HighwayHash-64) batched vs plain on 1 MI355X; p99 request latency"
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, published
-OUT_BYTES = 8                   # HighwayHash-64 result per message
+OUT_BYTES = 8                   # bytes per output word (HighwayHash-64: one word)
+# roofline.bound is "critical_path" when the longest chain covers at least
+# this fraction of the dominant kernel's time
+CRITICAL_BOUND_FRAC = 0.8
 KEY_BYTES = 32
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 # integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-op per
@@ -95,14 +107,14 @@ def parse_tuning(text: str) -> dict:
     return t
 
 
-def profile_applies(rec, kernel: str, workload_name: str, tuning: dict) -> bool:
+def profile_applies(rec, kernel: str, workload_name: str, tuning: dict, width: int = 1) -> bool:
     """A committed counter summary describes the timed launches only if it
-    was taken from the same kernel sources on the same workload and, for the
-    bucketed path's kernel (the only one the tuning changes), with the same
-    tuning."""
+    was taken from the same kernel sources on the same workload with the
+    same output width and, for the bucketed path's kernel (the only one the
+    tuning changes), with the same tuning."""
     if not rec or rec.get("source_sha") != kernel_source_sha(kernel):
         return False
-    if rec.get("workload") != workload_name:
+    if rec.get("workload") != workload_name or rec.get("width", 1) != width:
         return False
     if kernel == "hh_long_kernel":
         return rec.get("tuning") == {k: tuning[k] for k in TUNING_KEYS}
@@ -118,21 +130,41 @@ def tuning_tag(tuning: Optional[dict]) -> str:
                    if k in tuning and tuning[k] != DEFAULT_TUNING[k])
 
 
-def profile_file(kernel: str, workload: str, what: str, tuning: Optional[dict] = None) -> str:
+def width_tag(width: int) -> str:
+    """File-name tag of an output width other than one word, e.g. "_w4"."""
+    return "" if width == 1 else "_w%d" % width
+
+
+def profile_file(kernel: str, workload: str, what: str, tuning: Optional[dict] = None,
+                 width: int = 1) -> str:
     """Path of a committed counter summary; summaries of the bucketed
-    kernel taken with other than the default tuning carry its tag."""
-    return os.path.join(PROFILE_DIR, "%s_%s%s_%s.json" % (kernel, workload, tuning_tag(tuning),
-                                                          what))
+    kernel taken with other than the default tuning carry its tag, and
+    summaries of wider outputs their width."""
+    return os.path.join(PROFILE_DIR, "%s_%s%s%s_%s.json" % (kernel, workload, tuning_tag(tuning),
+                                                            width_tag(width), what))
 
 
-def find_profile(kernel: str, workload: str, what: str, workload_name: str, tuning: dict):
+def find_profile(kernel: str, workload: str, what: str, workload_name: str, tuning: dict,
+                 width: int = 1):
     """The committed summary that describes launches of `kernel` on this
-    workload with this tuning, or None."""
+    workload with this tuning and output width, or None."""
     for t in ((tuning,) if kernel == "hh_long_kernel" else ()) + (None,):
-        rec = load_json(profile_file(kernel, workload, what, t))
-        if profile_applies(rec, kernel, workload_name, tuning):
+        rec = load_json(profile_file(kernel, workload, what, t, width))
+        if profile_applies(rec, kernel, workload_name, tuning, width):
             return rec
     return None
+
+
+def binding_roof(hbm_frac, valu_frac, critical_ms, kernel_ms):
+    """(bound, bound_frac): the roof that binds the dominant kernel.  A chain
+    that covers at least CRITICAL_BOUND_FRAC of the kernel's time binds it
+    (its fraction: chain floor / kernel time); otherwise the larger of the
+    VALU and HBM fractions names the roof."""
+    if critical_ms and kernel_ms and critical_ms / kernel_ms >= CRITICAL_BOUND_FRAC:
+        return "critical_path", critical_ms / kernel_ms
+    if valu_frac is not None and (hbm_frac is None or valu_frac > hbm_frac):
+        return "alu", valu_frac
+    return "hbm", hbm_frac
 
 
 def kernel_source_sha(kernel: str = "hh_long_kernel") -> str:
@@ -206,16 +238,16 @@ def time_plain(hh, b, dev):
             "launches": len(groups), "kernel": "hh_thread_kernel (one thread per message)"}, got
 
 
-def time_single_launch(hh, b, dev, path):
+def time_single_launch(hh, b, dev, path, width=1):
     import torch
     k, ki, d, o, L = dev
-    out = torch.empty((b.n, 1), dtype=torch.int64, device="cuda")
-    hh.hash(k, d, o, L, ki, 1, path, out)
+    out = torch.empty((b.n, width), dtype=torch.int64, device="cuda")
+    hh.hash(k, d, o, L, ki, width, path, out)
     torch.cuda.synchronize()
     reps = 3
     t0 = time.perf_counter()
     for _ in range(reps):
-        hh.hash(k, d, o, L, ki, 1, path, out)
+        hh.hash(k, d, o, L, ki, width, path, out)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / reps
     return {"value": b.total_bytes / sec / 1e9, "unit": "GB/s", "ms": sec * 1e3}
@@ -232,7 +264,8 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(b, min_seconds: float = 10.0, max_reps: int = 64, single_bytes: int = 1 << 28):
+def cpu_baseline(b, min_seconds: float = 10.0, max_reps: int = 64, single_bytes: int = 1 << 28,
+                 width: int = 1):
     """The oracle's threaded batch driver over the whole batch on min(16,
     cores) threads, repeated until at least min_seconds of wall time (the
     median run is the value), plus one thread on a bounded sample (the
@@ -244,7 +277,7 @@ def cpu_baseline(b, min_seconds: float = 10.0, max_reps: int = 64, single_bytes:
     t0 = time.perf_counter()
     while True:
         t = time.perf_counter()
-        ref = oracle.batch(b.keys, b.key_idx, b.data, b.offsets, b.lengths, 1,
+        ref = oracle.batch(b.keys, b.key_idx, b.data, b.offsets, b.lengths, width,
                            n_threads=threads)
         runs.append(time.perf_counter() - t)
         if time.perf_counter() - t0 >= min_seconds or len(runs) >= max_reps:
@@ -269,7 +302,30 @@ def cpu_baseline(b, min_seconds: float = 10.0, max_reps: int = 64, single_bytes:
             "single_thread": {"value": sample_bytes / float(np.median(one)) / 1e9,
                               "unit": "GB/s", "sample": "the first %d messages (%d bytes), "
                               "3 runs, median" % (m, sample_bytes)},
-            "cpu_model": cpu_model(), "hardware_threads": os.cpu_count()}, ref[:, 0]
+            "cpu_model": cpu_model(), "hardware_threads": os.cpu_count()}, ref
+
+
+def serving_parity(trace, results) -> dict:
+    """Part of the CPU-baseline leg: the oracle's hash of every request of the
+    serving trace (each at its own width, on the host's cores) against the
+    result of that request at every load point."""
+    import numpy as np
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    bad = [0] * len(results)
+    for w in (1, 2, 4):
+        idx = np.flatnonzero(trace.width_words == w)
+        if not idx.size:
+            continue
+        ref = oracle.batch(trace.keys, trace.key_idx[idx], trace.data, trace.offsets[idx],
+                           trace.lengths[idx], w, n_threads=threads)
+        for p, res in enumerate(results):
+            got = res[idx, :w]
+            bad[p] += int(np.count_nonzero(np.any(got != ref, axis=1)))
+    return {"parity": "bit-exact" if not any(bad) else "MISMATCH",
+            "requests_checked_per_point": int(trace.n), "mismatches_per_point": bad,
+            "oracle_seconds": time.perf_counter() - t0, "oracle_threads": threads}
 
 
 def load_json(path):
@@ -300,6 +356,10 @@ def main(argv=None) -> int:
     ap.add_argument("--path", default=None, choices=sorted(PATH_KERNEL),
                     help="time this path with the library's tuning instead of the autotuned "
                          "one (prf: the counter-mode kernel, prf_counters workload only)")
+    ap.add_argument("--width", type=int, default=1, choices=[1, 2, 4],
+                    help="output words per message: 1 (HighwayHash-64, the default), 2 or 4 "
+                         "(the plain one-launch-per-length baseline is 64-bit only and is "
+                         "skipped for wider outputs)")
     args = ap.parse_args(argv)
     if args.path == "prf" and args.workload != "prf_counters":
         ap.error("--path prf needs --workload prf_counters")
@@ -328,7 +388,8 @@ def main(argv=None) -> int:
     gen_s = time.perf_counter() - t_gen
     dev = to_device(b)
     k, ki, d, o, L = dev
-    out = torch.empty((b.n, 1), dtype=torch.int64, device="cuda")
+    width = args.width
+    out = torch.empty((b.n, width), dtype=torch.int64, device="cuda")
 
     print("[bench] workload %s: %d messages, %d bytes (generated in %.1f s)"
           % (b.name, b.n, b.total_bytes, gen_s), file=sys.stderr, flush=True)
@@ -341,7 +402,7 @@ def main(argv=None) -> int:
         tuned = {"fixed": fixed_tuning}
     elif not args.no_autotune and args.path is None:
         from paper_1612_06257_amd import autotune
-        tuned = autotune.tune(k, d, o, L, ki, 1, cache_path=None)
+        tuned = autotune.tune(k, d, o, L, ki, width, cache_path=None)
         path = tuned["path"]
         if path == "bucketed":
             hh.set_tuning(**dict(hh.get_tuning(), **{x: tuned[x] for x in autotune.TUNING_KEYS}))
@@ -350,9 +411,9 @@ def main(argv=None) -> int:
 
     def step():
         if path == "prf":
-            hh.prf(k, b.n, 0, 1, out)
+            hh.prf(k, b.n, 0, width, out)
         else:
-            hh.hash(k, d, o, L, ki, 1, path, out)
+            hh.hash(k, d, o, L, ki, width, path, out)
 
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
@@ -386,12 +447,12 @@ def main(argv=None) -> int:
         sec = time.perf_counter() - t0
     ms_per_step = sec * 1e3 / args.steps
     value = b.total_bytes * args.steps / sec / 1e9
-    gpu_hash = hh.to_u64(out)[:, 0].copy()
+    gpu_hash = hh.to_u64(out).copy()
     print("[bench] batched: %.3f ms/step, %.1f GB/s" % (ms_per_step, value), file=sys.stderr,
           flush=True)
 
     # roofline of the dominant kernel: algorithmic bytes it moves per launch
-    # (message bytes read once, 8 output bytes per message, 32 per key) over
+    # (message bytes read once, 8 bytes per output word, 32 per key) over
     # its mean launch time; the PRF reads no message bytes (its counters are
     # built in registers)
     lengths = b.lengths.astype(np.int64)
@@ -402,12 +463,12 @@ def main(argv=None) -> int:
     else:
         mask = np.ones(lengths.shape, bool)
     msg_bytes = 0 if kernel == "hh_prf_kernel" else int(lengths[mask].sum())
-    kernel_bytes = msg_bytes + OUT_BYTES * int(mask.sum()) + KEY_BYTES * n_keys
+    kernel_bytes = msg_bytes + OUT_BYTES * width * int(mask.sum()) + KEY_BYTES * n_keys
     kernel_ms_mean = kernel_ms / launches if launches else None
     achieved = kernel_bytes / (kernel_ms_mean * 1e6) if kernel_ms_mean else None
     timed_tuning = hh.get_tuning()
     traffic = None
-    tr = find_profile(kernel, args.workload, "traffic", b.name, timed_tuning)
+    tr = find_profile(kernel, args.workload, "traffic", b.name, timed_tuning, width)
     if tr:
         traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "kernel": kernel, "achieved": achieved,
@@ -418,7 +479,7 @@ def main(argv=None) -> int:
     # integer-VALU roof of the same kernel, from its counted VALU instructions
     # (each a wave of 64 lane-ops) over the mean launch time measured above
     valu_roof = None
-    vc = find_profile(kernel, args.workload, "valu", b.name, timed_tuning)
+    vc = find_profile(kernel, args.workload, "valu", b.name, timed_tuning, width)
     if vc and kernel_ms_mean:
         c = vc["per_launch"]
         lane_ops = c["SQ_INSTS_VALU"] * 64.0
@@ -440,19 +501,19 @@ def main(argv=None) -> int:
             # streams measured to run concurrently (the runtime shares a few
             # hardware queues among streams; two on one queue serialise)
             streams = hh.independent_streams(n_streams, avoid=[])
-            outs = [torch.empty((b.n, 1), dtype=torch.int64, device="cuda")
+            outs = [torch.empty((b.n, width), dtype=torch.int64, device="cuda")
                     for _ in range(n_streams)]
             for s_, o_ in zip(streams, outs):      # each stream's workspace, warm
                 with torch.cuda.stream(s_):
-                    hh.hash(k, d, o, L, ki, 1, path, o_)
+                    hh.hash(k, d, o, L, ki, width, path, o_)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for i in range(args.steps):
                 with torch.cuda.stream(streams[i % n_streams]):
-                    hh.hash(k, d, o, L, ki, 1, path, outs[i % n_streams])
+                    hh.hash(k, d, o, L, ki, width, path, outs[i % n_streams])
             torch.cuda.synchronize()
             psec = time.perf_counter() - t0
-            exact = all(np.array_equal(hh.to_u64(x)[:, 0], gpu_hash) for x in outs)
+            exact = all(np.array_equal(hh.to_u64(x), gpu_hash) for x in outs)
             pipelined.append({"streams": n_streams, "value": b.total_bytes * args.steps / psec / 1e9,
                               "unit": "GB/s", "ms_per_batch": psec * 1e3 / args.steps,
                               "bit_exact": bool(exact)})
@@ -461,24 +522,38 @@ def main(argv=None) -> int:
                 file=sys.stderr, flush=True)
 
     # critical path: longest message x measured single-wave Update time
+    # (one thread per message on the lane1 and prf paths and for messages
+    # below the bucketed path's quad threshold, else four)
     chain = load_json(CHAIN_FILE) or {}
     ring = hh.get_tuning()["long_ring"]
-    t_upd_ns = chain.get("quad_loop_ring%d_ns_per_update" % ring) or chain.get("quad_ns_per_update")
     longest = int(lengths.max()) if lengths.size else 0
+    thread_layout = (path in ("lane1", "prf") or
+                     (path in ("auto", "bucketed") and longest < hh.get_tuning()["lane4_min_bytes"]))
+    if thread_layout:
+        t_upd_ns = chain.get("thread_ns_per_update")
+    else:
+        t_upd_ns = (chain.get("quad_loop_ring%d_ns_per_update" % ring)
+                    or chain.get("quad_ns_per_update"))
     n_upd = (longest + 31) // 32 + 4
     critical = None
     if t_upd_ns:
         floor_ms = n_upd * t_upd_ns * 1e-6
         critical = {"longest_message_bytes": longest, "updates": n_upd,
+                    "layout": "thread" if thread_layout else "quad",
                     "ns_per_update": t_upd_ns, "floor_ms": floor_ms,
-                    "frac_of_step": floor_ms / ms_per_step}
+                    "frac_of_step": floor_ms / ms_per_step,
+                    "frac_of_kernel": floor_ms / kernel_ms_mean if kernel_ms_mean else None}
+    bound, bound_frac = binding_roof(roofline["frac"], valu_roof["frac"] if valu_roof else None,
+                                     critical["floor_ms"] if critical else None, kernel_ms_mean)
+    roofline["bound"] = bound
+    roofline["bound_frac"] = bound_frac
 
     result = {
         "metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": b.name, "n_msgs": b.n, "bytes": b.total_bytes, "seed": b.seed,
-                   "output_bits": 64, "path": path, "tuning": hh.get_tuning()},
+                   "output_bits": 64 * width, "path": path, "tuning": hh.get_tuning()},
         "autotune": tuned,
         "messages_per_s": b.n * args.steps / sec,
         "roofline": roofline,
@@ -491,32 +566,43 @@ def main(argv=None) -> int:
     # the serving run goes first: the 27,560 launches of the plain baseline
     # leave the runtime slower for a while, which the serving latencies see
     result["serving"] = None
+    serving_check = None
     if not args.no_serving:
         from paper_1612_06257_amd import serve
-        result["serving"] = serve.bench_summary()
+        summary, trace, results = serve.bench_summary()
+        result["serving"] = summary
+        serving_check = (trace, results)
+        pts = [summary["saturation"]] + summary["loads"]
         print("[bench] serving: %s" % json.dumps(
-            {k: {"GBps": round(v["GBps"], 1), "p50_ms": round(v["p50_ms"], 3),
-                 "p99_ms": round(v["p99_ms"], 2)} for k, v in result["serving"].items()}),
-              file=sys.stderr, flush=True)
+            [{"load": v["load"], "GBps": round(v["GBps"], 1), "p50_ms": round(v["p50_ms"], 3),
+              "p99_ms": round(v["p99_ms"], 2)} for v in pts]), file=sys.stderr, flush=True)
 
-    if not args.no_plain:
+    if not args.no_plain and width == 1:
         plain, plain_hash = time_plain(hh, b, dev)
-        plain["bit_exact_with_batched"] = bool(np.array_equal(plain_hash, gpu_hash))
+        plain["bit_exact_with_batched"] = bool(np.array_equal(plain_hash, gpu_hash[:, 0]))
         result["plain"] = plain
         result["batched_over_plain"] = value / plain["value"]
-        result["single_launch"] = {p: time_single_launch(hh, b, dev, p) for p in ("lane1", "lane4")}
         print("[bench] plain: %d launches, %.1f ms" % (plain["launches"], plain["ms"]),
               file=sys.stderr, flush=True)
+    if not args.no_plain:
+        result["single_launch"] = {p: time_single_launch(hh, b, dev, p, width)
+                                   for p in ("lane1", "lane4")}
 
     if not args.no_cpu_baseline:
-        cb, ref = cpu_baseline(b)
+        cb, ref = cpu_baseline(b, width=width)
         result["cpu_baseline"] = cb
         result["parity"] = "bit-exact" if np.array_equal(ref, gpu_hash) else "MISMATCH"
+        if serving_check is not None:
+            result["serving"].update(serving_parity(*serving_check))
+            print("[bench] serving parity: %s" % result["serving"]["parity"], file=sys.stderr,
+                  flush=True)
     else:
         result["cpu_baseline"] = None
 
     print(json.dumps(result))
-    return 0 if result.get("parity", "bit-exact") == "bit-exact" else 3
+    ok = (result.get("parity", "bit-exact") == "bit-exact"
+          and (result["serving"] or {}).get("parity", "bit-exact") == "bit-exact")
+    return 0 if ok else 3
 
 
 if __name__ == "__main__":

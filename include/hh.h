@@ -32,6 +32,12 @@
  *   - Outputs are uint64 words, message-major, lane 0 first:
  *     out[w*j + i] is word i of message j's w-word hash.
  *   - `out` must not overlap any input.  n_msgs == 0 is a valid no-op.
+ *   - Threads: calls on different streams are independent.  Several host
+ *     threads may call on one stream (the null stream included): each call
+ *     enqueues its launches as one unit while holding the stream's library
+ *     workspace, so the calls run on the stream one after another, in the
+ *     order in which they took it.  (hh_hash_noalloc is the exception: see
+ *     there.)
  *   - Argument errors are reported synchronously (HH_ERR_INVALID_ARG) before
  *     any device call.  A device that is not gfx950 gives
  *     HH_ERR_UNSUPPORTED_DEVICE.  Faults of enqueued work surface at stream
@@ -174,8 +180,9 @@ hh_status hh_state_update(uint64_t* states, uint64_t n_states, const uint32_t* s
  * stream's total size mod 32 because earlier updates were whole packets),
  * finalizes (Sec. 4.3) and writes width_words[k] (1, 2 or 4; NULL = 1) words
  * to out[out_offsets[k] ..] (out_offsets NULL: out[4*k ..]); words at index
- * out_words or beyond are not written.  The stored state is not modified,
- * so a stream can be finished more than once. */
+ * out_words or beyond are not written, and an item whose width is not 1, 2
+ * or 4 writes nothing.  The stored state is not modified, so a stream can be
+ * finished more than once. */
 hh_status hh_state_final(uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
                          const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,
                          const uint64_t* lengths, const uint8_t* width_words, uint64_t* out,
@@ -184,7 +191,8 @@ hh_status hh_state_final(uint64_t* states, uint64_t n_states, const uint32_t* st
 
 /* One launch of mixed items (a serving iteration): item k with
  * width_words[k] == 0 is an update exactly as in hh_state_update; any other
- * width finishes as in hh_state_final.  width_words is required; out may be
+ * width finishes as in hh_state_final (widths other than 1, 2 and 4 leave
+ * the state as it is and write nothing).  width_words is required; out may be
  * NULL when no item finishes (out_words is then taken as 0). */
 hh_status hh_state_step(uint64_t* states, uint64_t n_states, const uint32_t* state_idx,
                         const uint8_t* data, uint64_t data_bytes, const uint64_t* offsets,

@@ -307,14 +307,19 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
 namespace {
 
 struct Workspace {
-    int device;
-    hipStream_t stream;
-    u8* mem;
-    u64 cap_msgs;
-    Plan* plan;
-    u32* long_list;
-    u32* order;
-    bool dirty;  // plan not known to be zero (new, or a sequence failed part-way)
+    int device = 0;
+    hipStream_t stream = nullptr;
+    u8* mem = nullptr;
+    u64 cap_msgs = 0;
+    Plan* plan = nullptr;
+    u32* long_list = nullptr;
+    u32* order = nullptr;
+    bool dirty = false;  // plan not known to be zero (new, or a sequence failed part-way)
+    // held from the lookup of the workspace through the last launch of a
+    // sequence: host threads that share a stream enqueue whole sequences one
+    // after another (interleaved launches would mix their plans), and none
+    // regrows the buffers while another enqueues against them
+    std::mutex mu;
 };
 
 std::mutex g_ws_mutex;
@@ -381,15 +386,22 @@ u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
 
 void drop_graphs_of(const u8* ws_mem);
 
-hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out) {
-    std::lock_guard<std::mutex> lock(g_ws_mutex);
+// The workspace of (dev, st), grown to hold n messages, returned with its
+// mutex held by `hold` (the caller keeps it until its launches are enqueued).
+hh_status get_workspace(int dev, hipStream_t st, u64 n, Workspace** out,
+                        std::unique_lock<std::mutex>* hold) {
     Workspace* ws = nullptr;
-    for (auto& w : g_ws)
-        if (w.device == dev && w.stream == st) ws = &w;
-    if (!ws) {
-        g_ws.push_back(Workspace{dev, st, nullptr, 0, nullptr, nullptr, nullptr, false});
-        ws = &g_ws.back();
+    {
+        std::lock_guard<std::mutex> lock(g_ws_mutex);
+        for (auto& w : g_ws)
+            if (w.device == dev && w.stream == st) ws = &w;
+        if (!ws) {
+            ws = &g_ws.emplace_back();
+            ws->device = dev;
+            ws->stream = st;
+        }
     }
+    *hold = std::unique_lock<std::mutex>(ws->mu);
     if (ws->cap_msgs < n || !ws->mem) {
         u64 cap = ws->cap_msgs ? ws->cap_msgs : 1024;
         while (cap < n) cap *= 2;
@@ -637,14 +649,14 @@ hh_status launch_bucketed_noalloc(const HashArgs& a, hipStream_t st) {
     if (s != HH_OK) return s;
     u8* base = nullptr;
     if ((s = scratch_address(dev, &base)) != HH_OK) return s;
-    Workspace ws{dev,
-                 st,
-                 base,
-                 HH_NOALLOC_MAX_MSGS,
-                 (Plan*)base,
-                 (u32*)(base + kNoallocPlanBytes),
-                 (u32*)(base + kNoallocPlanBytes + kNoallocListBytes),
-                 false};
+    Workspace ws;
+    ws.device = dev;
+    ws.stream = st;
+    ws.mem = base;
+    ws.cap_msgs = HH_NOALLOC_MAX_MSGS;
+    ws.plan = (Plan*)base;
+    ws.long_list = (u32*)(base + kNoallocPlanBytes);
+    ws.order = (u32*)(base + kNoallocPlanBytes + kNoallocListBytes);
     const DeviceInfo di = device_info(dev);
     const hh_tuning tun = current_tuning();
     const LaunchShape ls = launch_shape(a, di, tun);
@@ -675,7 +687,8 @@ hh_status launch_bucketed(const HashArgs& a, hipStream_t st) {
         c.key_idx = a.key_idx ? a.key_idx + first : nullptr;
         c.out = a.out + first * a.width;
         Workspace* ws = nullptr;
-        if ((s = get_workspace(dev, st, c.n, &ws)) != HH_OK) return s;
+        std::unique_lock<std::mutex> hold;
+        if ((s = get_workspace(dev, st, c.n, &ws, &hold)) != HH_OK) return s;
         switch (a.width) {
             case 1: s = launch_bucketed_w<1>(c, st, ws, di, tun); break;
             case 2: s = launch_bucketed_w<2>(c, st, ws, di, tun); break;

@@ -182,7 +182,10 @@ __global__ __launch_bounds__(256) void hh_state_step_kernel(
             if (r) remainder1(s, r, tail);
             const u64 sum = finalize1(s);
             const u64 o = out_offsets ? out_offsets[k] : 4 * k;
-            if (real && (u32)q < w && o < out_words && (u64)q < out_words - o) out[o + q] = sum;
+            // widths other than 1, 2 and 4 write nothing
+            const bool valid_w = w == 1u || w == 2u || w == 4u;
+            if (real && valid_w && (u32)q < w && o < out_words && (u64)q < out_words - o)
+                out[o + q] = sum;
         }
     }
 }

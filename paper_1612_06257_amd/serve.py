@@ -665,36 +665,56 @@ def serve_trace(trace, budget_bytes: int = 32 << 30, chunk_bytes: int = 1 << 16,
     return m, reqs
 
 
+def results_array(reqs: List[Request], n: int) -> np.ndarray:
+    """(n, 4) uint64 results by request id (words past a request's width and
+    unfinished requests are 0)."""
+    out = np.zeros((n, 4), np.uint64)
+    for r in reqs:
+        if r.result is not None:
+            out[r.rid, :len(r.result)] = r.result
+    return out
+
+
 def load_sweep(n_requests: int = 10000, loads=(0.25, 0.5, 0.8), chunk_bytes: int = 1 << 16,
                budget_bytes: int = 32 << 30, source: str = "device", seed: Optional[int] = None,
-               **server_kw):
+               with_results: bool = False, **server_kw):
     """Saturation run (every request arrives at t=0), then Poisson loads at
-    the given fractions of the measured saturation request rate."""
+    the given fractions of the measured saturation request rate.  Every point
+    serves the same requests (lengths, payloads, keys, widths).  With
+    with_results, returns (points, trace, per-point results_array)."""
     from . import workloads as W
     kw = {} if seed is None else {"seed": seed}
     base = W.serving_trace(n_requests, 1.0, **kw)
     base.arrival_s[:] = 0.0
-    sat, _ = serve_trace(base, budget_bytes, chunk_bytes, source=source, **server_kw)
+    sat, reqs = serve_trace(base, budget_bytes, chunk_bytes, source=source, **server_kw)
     sat_rate = sat["requests_per_s"]
     out = [dict(sat, load="saturation", offered_requests_per_s=None)]
+    results = [results_array(reqs, base.n)] if with_results else None
     for f in loads:
         tr = W.serving_trace(n_requests, f * sat_rate, materialize=False, **kw)
         tr.data, tr.offsets, tr.lengths = base.data, base.offsets, base.lengths
         tr.key_idx, tr.width_words, tr.keys = base.key_idx, base.width_words, base.keys
-        m, _ = serve_trace(tr, budget_bytes, chunk_bytes, source=source, **server_kw)
+        m, reqs = serve_trace(tr, budget_bytes, chunk_bytes, source=source, **server_kw)
         out.append(dict(m, load=f, offered_requests_per_s=f * sat_rate))
-    return out
+        if with_results:
+            results.append(results_array(reqs, base.n))
+    return (out, base, results) if with_results else out
 
 
-def bench_summary(n_requests: int = 2000, load: float = 0.5, chunk_bytes: int = 1 << 16) -> dict:
-    """Short run for the benchmark line: a discarded warm-up pass (first-use
-    allocations, clocks), then saturation plus one Poisson load."""
+def bench_summary(n_requests: int = 10000, loads=(0.25, 0.5, 0.8),
+                  chunk_bytes: int = 1 << 16):
+    """The benchmark's serving run: a discarded warm-up pass (first-use
+    allocations, clocks), then saturation and the Poisson loads, all with the
+    same requests.  Returns (summary, trace, per-point results) so that the
+    caller can check every result."""
     from . import workloads as W
     warm = W.serving_trace(400, 1.0, seed=W.SEED_BASE + 99)
     warm.arrival_s[:] = 0.0
     serve_trace(warm, chunk_bytes=chunk_bytes)
-    pts = load_sweep(n_requests, (load,), chunk_bytes)
-    return {"saturation": pts[0], "load": pts[1]}
+    pts, trace, results = load_sweep(n_requests, loads, chunk_bytes, with_results=True)
+    summary = {"requests_per_point": n_requests, "saturation": pts[0],
+               "loads": pts[1:]}
+    return summary, trace, results
 
 
 def main(argv=None):

@@ -313,3 +313,48 @@ def test_calls_from_several_host_threads(hh):
     for t, outs in results.items():
         for i, got in enumerate(outs):
             assert_same(got, want, "thread %d call %d" % (t, i))
+
+
+@pytest.mark.parametrize("shared", ["stream", "null"])
+def test_host_threads_sharing_one_stream(hh, shared):
+    # four host threads call the bucketed path on ONE stream (a shared torch
+    # stream, or the null stream that is every thread's default), each with
+    # its own batch of a different size, so the workspace is looked up, grown
+    # and enqueued against from several threads at once; each call's
+    # sequence must stay whole on the stream and every result exact
+    import threading
+    announce("threads sharing", shared)
+    batches = [_batch(seed=95 + t, n=600 + 900 * t) for t in range(4)]
+    wants = [oracle_ref(1, *b) for b in batches]
+    devs = [batch_to_device(*b) for b in batches]
+    stream = torch.cuda.Stream() if shared == "stream" else None
+    results, errors = {}, []
+    start = threading.Barrier(4)
+
+    def work(t):
+        try:
+            k, ki, d, o, L = devs[t]
+            outs = []
+            start.wait(timeout=30)
+            if stream is None:
+                for _ in range(6):
+                    outs.append(hh.hash(k, d, o, L, ki, 1, "bucketed"))
+            else:
+                with torch.cuda.stream(stream):
+                    for _ in range(6):
+                        outs.append(hh.hash(k, d, o, L, ki, 1, "bucketed"))
+            results[t] = outs
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=60)
+    torch.cuda.synchronize()
+    assert not errors, errors
+    assert sorted(results) == [0, 1, 2, 3]
+    for t, outs in results.items():
+        for i, got in enumerate(outs):
+            assert_same(hh.to_u64(got), wants[t], "%s: thread %d call %d" % (shared, t, i))

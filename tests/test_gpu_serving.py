@@ -157,3 +157,81 @@ def test_state_step_mixed_equals_separate_calls(hh):
     hh.state_update(b, data, offs[upd.long()], lens[upd.long()], upd)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_widths_other_than_1_2_4_write_nothing(hh):
+    # hh_state_final and hh_state_step: an item of width 3, 5, 8 or 255
+    # writes no output word and leaves its state as it is; the valid items
+    # of the same launch are unaffected
+    announce("state widths out of contract")
+    rng = np.random.default_rng(14)
+    keys = torch.from_numpy(rng.integers(0, 2**64, (1, 4), dtype=np.uint64)).view(
+        torch.int64).cuda()
+    d_np = rng.integers(0, 256, 1 << 14, dtype=np.uint8)
+    data = torch.from_numpy(d_np).cuda()
+    widths = np.array([3, 1, 255, 2, 5, 4, 8, 0], np.uint8)
+    n = widths.size
+    offs_np = rng.integers(0, 10000, n).astype(np.int64)
+    lens_np = rng.integers(1, 3000, n).astype(np.int64)
+    lens_np[widths == 0] &= ~31
+    offs, lens = torch.from_numpy(offs_np).cuda(), torch.from_numpy(lens_np).cuda()
+    ww = torch.from_numpy(widths).cuda()
+    key = keys.cpu().numpy().view(np.uint64)[0]
+    for fn in ("final", "step"):
+        states = hh.state_init(keys, n)
+        before = states.clone()
+        out = torch.full((n, 4), -7, dtype=torch.int64, device="cuda")
+        if fn == "final":
+            hh.state_final(states, data, offs, lens, ww, out.view(-1))
+        else:
+            hh.state_step(states, data, offs, lens, ww, out.view(-1))
+        torch.cuda.synchronize()
+        got = hh.to_u64(out)
+        for k, w in enumerate(widths.tolist()):
+            if w in (1, 2, 4):
+                msg = d_np[offs_np[k]:offs_np[k] + lens_np[k]].tobytes()
+                want = [int(x) for x in oracle.hash_words(key, msg, w)]
+                assert got[k][:w].tolist() == want, (fn, k, w)
+                assert (out[k, w:] == -7).all(), (fn, k, w)
+            elif fn == "final" or w != 0:
+                assert (out[k] == -7).all(), (fn, k, w)
+        fin = torch.from_numpy(widths != 0).cuda() if fn == "step" else torch.ones(
+            n, dtype=torch.bool, device="cuda")
+        assert torch.equal(states[fin], before[fin]), fn
+
+
+@pytest.mark.parametrize("arrivals", ["saturation", "poisson"])
+def test_serving_at_benchmark_settings(hh, arrivals):
+    # the settings the benchmark's serving runs use: 64 KiB chunks, 1 MiB
+    # long-lane chunks, power-law lengths on [8 B, 16 MiB], 64 keys, widths
+    # 1/2/4, device ingress; a few requests of 4-16 MiB span many long-lane
+    # iterations beside the short ones.  Every result equals the oracle and
+    # the request hashed on its own by the one-shot batched path.
+    from paper_1612_06257_amd import workloads as W
+    announce("serving at bench settings", arrivals)
+    tr = W.serving_trace(500, 40000.0, seed=W.SEED_BASE + 77, materialize=False)
+    lens = tr.lengths.copy()
+    lens[[3, 97, 211, 402]] = [1 << 24, (1 << 24) - 1, (5 << 20) + 17, (4 << 20) + 32]
+    lens[[5, 6]] = [8, 31]
+    rng = np.random.default_rng(77)
+    tr.lengths = lens
+    tr.offsets = (np.cumsum(lens) - lens).astype(np.uint64)
+    tr.data = rng.integers(0, 256, int(lens.sum()), dtype=np.uint8)
+    if arrivals == "saturation":
+        tr.arrival_s[:] = 0.0
+    m, reqs = serve.serve_trace(tr, chunk_bytes=1 << 16, long_chunk_bytes=1 << 20)
+    assert m["completed"] == len(reqs) == tr.n
+    got = {r.rid: r.result for r in reqs}
+    keys = torch.from_numpy(tr.keys).view(torch.int64).cuda()
+    data = torch.from_numpy(tr.data).cuda()
+    for w in (1, 2, 4):
+        idx = np.flatnonzero(tr.width_words == w)
+        want = oracle.batch(tr.keys, tr.key_idx[idx], tr.data, tr.offsets[idx], tr.lengths[idx],
+                            w)
+        alone = hh.to_u64(hh.hash(keys, data, torch.from_numpy(tr.offsets[idx].astype(
+            np.int64)).cuda(), torch.from_numpy(tr.lengths[idx].astype(np.int64)).cuda(),
+            torch.from_numpy(tr.key_idx[idx].astype(np.int32)).cuda(), w))
+        torch.cuda.synchronize()
+        for row, i in enumerate(idx.tolist()):
+            assert got[i] == tuple(int(x) for x in want[row]), ("oracle", i, w, tr.lengths[i])
+            assert got[i] == tuple(int(x) for x in alone[row]), ("alone", i, w, tr.lengths[i])
