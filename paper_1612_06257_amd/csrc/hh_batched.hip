@@ -11,21 +11,27 @@
 //
 // Launch sequence on one stream (all device-side, no host synchronisation;
 // optionally captured once per argument set into a hipGraph and replayed):
-//   (hh_plan_reset_kernel  zero the plan: only after a sequence that failed
-//                          part-way; the last wave of hh_long_kernel zeroes
-//                          it otherwise)
+//   (hh_plan_reset_kernel  zero the plan: before a workspace's first sequence
+//                          and after a sequence that failed part-way)
 //   hh_split_kernel<W>     L < threshold: hash in-thread;  else: append the
 //                          index to the long list and count it in its length
 //                          bucket (8 buckets per octave of the packet count)
 //   hh_scatter_kernel      bucket start offsets (longest bucket first, every
 //                          block recomputes the 256-entry prefix), then long
 //                          list -> bucket order; block 0 also decides how many
-//                          leading (critical) items get a CU of their own
+//                          leading (critical) items get a CU of their own,
+//                          publishes the list length and clears the item
+//                          counter for the persistent kernel
 //   hh_long_kernel<W>      persistent: critical item b on wave 0 of workgroup
 //                          b, the other waves of that workgroup idle; every
 //                          other wave takes one item (16 messages, 4 threads
-//                          each), then items from an atomic counter; the last
-//                          wave to finish zeroes the plan
+//                          each), then items from an atomic counter; one wave
+//                          clears the split and scatter counters for the next
+//                          sequence
+// Every counter is cleared by a kernel that runs after its last reader and
+// before its next writer, so no kernel counts its retiring waves: device-scope
+// atomics on one address serialise, and a retire counter cost the persistent
+// kernel about 13 us on an empty long list.
 // A chain slows down by about 10% when other waves of its CU stream data
 // alongside it (they share the CU's load path), which is why the few chains
 // that set the batch's duration run alone on their CUs when the rest of the
@@ -46,13 +52,14 @@ namespace hh {
 constexpr int kBuckets = 256;
 constexpr u64 kPriorityBytes = 64u << 10;  // items this long run at wave priority 3
 
+// Who writes and who clears each field (one sequence: split, scatter, long):
 struct Plan {
-    u32 n_long;     // messages appended to the long list
-    u32 item_next;  // next dynamic item of hh_long_kernel
-    u32 n_iso;       // leading items that get a CU each
-    u32 waves_done;  // waves of hh_long_kernel that have retired
-    u32 hist[kBuckets];
-    u32 cursor[kBuckets];
+    u32 n_long;     // split appends; scatter reads; long clears
+    u32 item_next;  // long takes dynamic items; scatter clears
+    u32 n_iso;      // scatter: leading items that get a CU each
+    u32 n_order;    // scatter: entries of the ordered list (long reads)
+    u32 hist[kBuckets];    // split counts; scatter reads; long clears
+    u32 cursor[kBuckets];  // scatter reserves; long clears
 };
 
 // length bucket of a message with npk whole packets: 8 per octave,
@@ -163,13 +170,17 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
     __shared__ u32 base[kBuckets];
     __shared__ u32 start[kBuckets];
     __shared__ unsigned long long total_packets;
+    __shared__ u32 iso_s;
     // bucket starts: exclusive prefix over buckets, longest bucket first
     {
         const u32 t = threadIdx.x;
         const u32 b = kBuckets - 1u - t;
         const u32 c = plan->hist[b];
         cnt[t] = c;
-        if (t == 0u) total_packets = 0ull;
+        if (t == 0u) {
+            total_packets = 0ull;
+            iso_s = 0u;
+        }
         __syncthreads();
         if (blockIdx.x == 0 && c)
             atomicAdd(&total_packets, (unsigned long long)c * bucket_floor(b));
@@ -188,9 +199,17 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
             const u32 top = cnt[t + 7u < kBuckets ? t + 7u : kBuckets - 1u];
             const u32 items = (top + 15u) >> 4;
             const bool light = total_packets <= bucket_floor(b) * kIsoPacketsPerChainPacket;
-            plan->n_iso = (items <= iso_cap && light) ? items : 0u;
+            iso_s = (items <= iso_cap && light) ? items : 0u;
         }
         __syncthreads();
+        // for the persistent kernel, which runs after this one: the list
+        // length, the critical items and a cleared item counter (the long
+        // kernel of the previous sequence, its last user, has finished)
+        if (blockIdx.x == 0 && t == 0u) {
+            plan->n_order = min(plan->n_long, n);
+            plan->n_iso = iso_s;
+            plan->item_next = 0u;
+        }
     }
     // the plan is this stream's own and zero before the split kernel ran, so
     // these bounds never bind; they keep every access inside the lists and
@@ -225,20 +244,17 @@ __global__ __launch_bounds__(kBuckets) void hh_scatter_kernel(
     }
 }
 
-// Called by every wave of hh_long_kernel as its last action.  The last wave
-// to retire zeroes the plan for the next call on this workspace (the calls of
-// a workspace are ordered on its stream).  No fence is needed: every plan
-// access of a wave (loads, the item counter's atomic) has returned a value
-// the wave used before it counts itself, and the end of the kernel makes the
-// zeros visible to the next one.  (A device-scope fence here would write back
-// the L2 of the wave's XCD, once per wave.)
-__device__ __forceinline__ void retire_wave(Plan* plan, u32 total_waves, u32 lane) {
-    u32 prev = 0;
-    if (lane == 0) prev = atomicAdd(&plan->waves_done, 1u);
-    prev = __builtin_amdgcn_readfirstlane(prev);
-    if (prev == total_waves - 1u) {
-        u32* w = (u32*)plan;
-        for (u32 i = lane; i < sizeof(Plan) / 4; i += 64u) w[i] = 0u;
+// Run by one wave of hh_long_kernel: clear the split and scatter counters for
+// the next sequence on this workspace (their last readers, the split and
+// scatter kernels of this sequence, have finished; the calls of a workspace
+// are ordered on its stream, and the end of this kernel makes the zeros
+// visible to the next split kernel).  The persistent kernel reads none of
+// these fields.
+__device__ __forceinline__ void clear_split_counters(Plan* plan, u32 lane) {
+    if (lane == 0) plan->n_long = 0u;
+    for (u32 i = lane; i < kBuckets; i += 64u) {
+        plan->hist[i] = 0u;
+        plan->cursor[i] = 0u;
     }
 }
 
@@ -247,7 +263,7 @@ __device__ __forceinline__ void retire_wave(Plan* plan, u32 total_waves, u32 lan
 // waves of that workgroup (one workgroup per CU) exit, so the critical chain
 // has the CU to itself.  The remaining waves take items n_iso.. first,
 // numbered so that consecutive items land on distinct workgroups, then items
-// from plan->item_next.
+// from plan->item_next (only when such dynamic items exist).
 template <int W, int RING>
 __global__ __launch_bounds__(256) void hh_long_kernel(
     const u64* __restrict__ keys, u32 n_keys, const u32* __restrict__ key_idx,
@@ -257,32 +273,38 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
     extern __shared__ u32 lds_reserve[];  // sized by the launch to set residency
     const u32 lane = threadIdx.x & 63u;
     const int q = (int)(lane & 3u);
-    const u32 n_long = min(plan->n_long, n);  // never binds (see the scatter kernel)
+    const u32 n_long = min(plan->n_order, n);  // never binds (see the scatter kernel)
     const u32 n_items = (n_long + 15u) >> 4;
     const u32 groups = gridDim.x, g = blockIdx.x, w = threadIdx.x >> 6;
-    const u32 n_iso = plan->n_iso;  // at most a quarter of the workgroups
-    const u32 total_waves = groups * 4u;
+    const u32 n_iso = min(plan->n_iso, groups);  // at most a quarter of the workgroups
+    if (g == 0u && w == 3u) clear_split_counters(plan, lane);
     u32 item;
     if (g < n_iso) {
-        if (w != 0u) {
-            retire_wave(plan, total_waves, lane);
-            return;
-        }
+        if (w != 0u) return;
         item = g;
     } else {
         item = n_iso + w * (groups - n_iso) + (g - n_iso);
     }
     const u32 first_dynamic = n_iso + 4u * (groups - n_iso);
+    const bool dynamic = first_dynamic < n_items;
     if (item >= n_items && threadIdx.x == 0) lds_reserve[0] = 0u;
     while (item < n_items) {
         const u32 k = 16u * item + (lane >> 2);
         // items come longest first: the item's first message decides whether
         // this wave's chain is long enough to claim its SIMD's issue slots
         const u32 first = min(__builtin_amdgcn_readfirstlane(order[16u * item]), n - 1u);
-        if (lengths[first] >= kPriorityBytes)
+        const bool long_item = lengths[first] >= kPriorityBytes;
+        if (long_item)
             __builtin_amdgcn_s_setprio(3);
         else
             __builtin_amdgcn_s_setprio(0);
+        // a short item reserves the wave's next item now, so that the
+        // atomic's round trip overlaps the item; a long one (its time dwarfs
+        // the round trip) takes the next item only when it is done, so that
+        // no item waits behind it
+        u32 nxt = n_items;
+        if (dynamic && !long_item && lane == 0)
+            nxt = first_dynamic + atomicAdd(&plan->item_next, 1u);
         // the quads of a ragged last item repeat the item's first message
         // (same cache lines) and store nothing: the wave keeps all lanes on
         {
@@ -294,11 +316,10 @@ __global__ __launch_bounds__(256) void hh_long_kernel(
             const u64 sum = hash_quad<RING>(key_q, m.p, m.len, q);
             if (real && q < W) out[(u64)W * j + q] = sum;
         }
-        u32 nxt = 0;
-        if (lane == 0) nxt = first_dynamic + atomicAdd(&plan->item_next, 1u);
+        if (dynamic && long_item && lane == 0)
+            nxt = first_dynamic + atomicAdd(&plan->item_next, 1u);
         item = __builtin_amdgcn_readfirstlane(nxt);
     }
-    retire_wave(plan, total_waves, lane);
 }
 
 // ---------------------------------------------------------------------------
