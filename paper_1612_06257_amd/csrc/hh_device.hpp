@@ -138,13 +138,42 @@ __device__ __forceinline__ void update4(State4& s, const u64 p[4]) {
     for (int i = 0; i < 4; ++i) s.v1[i] += z[i];
 }
 
+// x + rot32(y): the halves of y are added crosswise with a 32-bit add and an
+// add-with-carry, so rot32(y) is never formed in a register pair (which costs
+// two moves before a 64-bit add).
+__device__ __forceinline__ u64 add_rot32(u64 x, u64 y) {
+    unsigned int carry = 0;
+    const u32 lo = __builtin_addc(lo32(x), hi32(y), 0u, &carry);
+    const u32 hi = __builtin_addc(hi32(x), lo32(y), carry, &carry);
+    return make64(lo, hi);
+}
+
+// Update(Permute(v0)) (Sec. 4.3): the packet is Permute(v0)[i] = rot32(v0[i^2]),
+// taken before the Update changes v0; otherwise update4.
+__device__ __forceinline__ void update4_permuted(State4& s) {
+    const u64 q[4] = {s.v0[2], s.v0[3], s.v0[0], s.v0[1]};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        s.v1[i] = add_rot32(s.v1[i] + s.mul0[i], q[i]);
+        s.mul0[i] ^= mul_lo_hi(s.v1[i], s.v0[i]);
+        s.v0[i] += s.mul1[i];
+        s.mul1[i] ^= mul_lo_hi(s.v0[i], s.v1[i]);
+    }
+    u64 z[4];
+    zipper_pair(s.v1[0], s.v1[1], z[0], z[1]);
+    zipper_pair(s.v1[2], s.v1[3], z[2], z[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s.v0[i] += z[i];
+    zipper_pair(s.v0[0], s.v0[1], z[0], z[1]);
+    zipper_pair(s.v0[2], s.v0[3], z[2], z[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s.v1[i] += z[i];
+}
+
 // Sec. 4.3: four rounds of Update(Permute(v0)); Permute(v0)[i] = rot32(v0[i^2]).
 __device__ __forceinline__ void finalize4(State4& s, u64 sum[4]) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const u64 p[4] = {rot32(s.v0[2]), rot32(s.v0[3]), rot32(s.v0[0]), rot32(s.v0[1])};
-        update4(s, p);
-    }
+    for (int k = 0; k < 4; ++k) update4_permuted(s);
 #pragma unroll
     for (int i = 0; i < 4; ++i) sum[i] = s.v0[i] + s.v1[i] + s.mul0[i] + s.mul1[i];
 }
