@@ -2,17 +2,21 @@
 
     python -m paper_1612_06257_amd.profiles_summary stats  <kernel_stats.csv> <out.md> <command>
     python -m paper_1612_06257_amd.profiles_summary traffic <fetch.csv> <write.csv> \
-        <copy_fetch.csv> <copy_write.csv> <copy_bytes> <workload> <out.json>
-    python -m paper_1612_06257_amd.profiles_summary valu <sq.csv> <workload> <out.json> \
-        [<kernel prefix> [<bench.py arguments of the profiled run>]]
+        <copy_fetch.csv> <copy_write.csv> <copy_bytes> <workload> <out.json> [options]
+    python -m paper_1612_06257_amd.profiles_summary valu <sq.csv> <workload> <out.json> [options]
 
-`traffic` and `valu` take `--tuning JSON`: the hh_tuning the profiled runs
-were given with `bench.py --tuning`, recorded so that a benchmark reuses the
-figures only for launches made with that tuning.
+options:
+  --kernel PREFIX      the kernel to summarise (default hh::hh_long_kernel<1)
+  --bench-args ARGS    the bench.py arguments of the profiled runs (recorded
+                       in the summary's commands)
+  --tuning JSON        the hh_tuning the profiled runs were given with
+                       bench.py --tuning, recorded so that a benchmark reuses
+                       the figures only for launches made with that tuning
+  --width N            output words per message of the profiled runs
 
-`traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of
-hh_long_kernel by the factor that makes the same counters read the known size
-of a plain copy kernel, and records the hash of the kernel sources so that a
+`traffic` scales the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of the
+kernel by the factor that makes the same counters read the known size of a
+plain copy kernel, and records the hash of the kernel sources so that a
 later benchmark only reuses the figure while the kernel is unchanged.
 """
 import csv
@@ -50,7 +54,7 @@ def _tuning_arg(tuning):
 
 
 def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
-            kernel_prefix="hh::hh_long_kernel<1", tuning=None):
+            kernel_prefix="hh::hh_long_kernel<1", tuning=None, bench_args=None, width=1):
     sys.path.insert(0, ".")
     import bench
     f = _per_kernel(fetch)
@@ -67,12 +71,12 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, workload, out,
         "fetch_scale": f_factor, "write_scale": w_factor,
         "hbm_bytes_per_launch": f[kernel] * 1024.0 * f_factor + w[kernel] * 1024.0 * w_factor,
         "other_kernels_fetch_kib": {k: v for k, v in f.items() if k != kernel},
-        "tuning": tuning,
+        "tuning": tuning, "width": width,
         "commands": [
             "rocprofv3 --pmc FETCH_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py "
-            + BENCH_ARGS + _tuning_arg(tuning),
+            + (bench_args or BENCH_ARGS) + _tuning_arg(tuning),
             "rocprofv3 --pmc WRITE_SIZE -d <dir> -o bench --output-format csv -- python -u bench.py "
-            + BENCH_ARGS + _tuning_arg(tuning),
+            + (bench_args or BENCH_ARGS) + _tuning_arg(tuning),
             "rocprofv3 --pmc FETCH_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
             "rocprofv3 --pmc WRITE_SIZE -d <dir> -o copy --output-format csv -- python -u -m paper_1612_06257_amd.microbench --copy-only %d" % copy_bytes,
         ],
@@ -92,7 +96,7 @@ BENCH_ARGS = ("--steps 2 --warmup 1 --no-cpu-baseline --no-plain --no-autotune -
 
 
 def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1", bench_args=BENCH_ARGS,
-         tuning=None):
+         tuning=None, width=1):
     """Per-dispatch means of the SQ counters of one kernel (one rocprofv3
     --pmc run of bench.py with VALU_COUNTERS), with the kernel-source hash."""
     sys.path.insert(0, ".")
@@ -107,7 +111,7 @@ def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1", bench_args=B
            "source_sha": bench.kernel_source_sha(_base(kernel)),
            "per_launch": {c: sum(v) / len(v) for c, v in sorted(per.items())},
            "launches": len(next(iter(per.values()))),
-           "tuning": tuning,
+           "tuning": tuning, "width": width,
            "command": "rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " -d <dir> -o bench "
                       "--output-format csv -- python -u bench.py " + bench_args
                       + _tuning_arg(tuning)}
@@ -116,17 +120,35 @@ def valu(path, workload, out, kernel_prefix="hh::hh_long_kernel<1", bench_args=B
     return rec
 
 
+def _options(argv):
+    """Split --kernel/--bench-args/--tuning/--width from the positional
+    arguments."""
+    opts = {"kernel_prefix": "hh::hh_long_kernel<1", "bench_args": None, "tuning": None,
+            "width": 1}
+    names = {"--kernel": "kernel_prefix", "--bench-args": "bench_args", "--tuning": "tuning",
+             "--width": "width"}
+    pos = []
+    i = 0
+    while i < len(argv):
+        if argv[i] in names:
+            key = names[argv[i]]
+            val = argv[i + 1]
+            opts[key] = json.loads(val) if key == "tuning" else int(val) if key == "width" else val
+            i += 2
+        else:
+            pos.append(argv[i])
+            i += 1
+    return pos, opts
+
+
 if __name__ == "__main__":
-    argv = sys.argv[1:]
-    tuning = None
-    if "--tuning" in argv:
-        i = argv.index("--tuning")
-        tuning = json.loads(argv[i + 1])
-        del argv[i:i + 2]
-    if argv[0] == "stats":
-        kernel_stats(argv[1], argv[2], argv[3])
-    elif argv[0] == "valu":
-        print(json.dumps(valu(*argv[1:6], tuning=tuning), indent=1))
+    pos, opts = _options(sys.argv[1:])
+    if pos[0] == "stats":
+        kernel_stats(pos[1], pos[2], pos[3])
+    elif pos[0] == "valu":
+        if opts["bench_args"] is None:
+            opts["bench_args"] = BENCH_ARGS
+        print(json.dumps(valu(pos[1], pos[2], pos[3], **opts), indent=1))
     else:
-        print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], int(argv[5]), argv[6],
-                                 argv[7], tuning=tuning), indent=1))
+        print(json.dumps(traffic(pos[1], pos[2], pos[3], pos[4], int(pos[5]), pos[6], pos[7],
+                                 **opts), indent=1))
