@@ -409,11 +409,15 @@ def main(argv=None) -> int:
         print("[bench] autotuned: %s" % json.dumps(tuned), file=sys.stderr, flush=True)
     kernel = PATH_KERNEL[path]
 
+    # the steps make the C call with arguments checked and marshalled once
+    # (as a C caller would); the PRF takes no per-message arguments
+    call = None if path == "prf" else hh.prepare(k, d, o, L, ki, width, path, out, stream)
+
     def step():
-        if path == "prf":
+        if call is None:
             hh.prf(k, b.n, 0, width, out)
         else:
-            hh.hash(k, d, o, L, ki, width, path, out)
+            call()
 
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):

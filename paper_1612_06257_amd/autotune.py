@@ -132,11 +132,15 @@ def tune(keys, data, offsets, lengths, key_idx=None, width: int = 1, reps: int =
     out = torch.empty((offsets.numel(), width), dtype=torch.int64, device=offsets.device)
     stream = torch.cuda.Stream()
 
+    # one prepared call per path: the timings measure the library call, not
+    # the binding's argument checks
+    calls = {p: hh.prepare(keys, data, offsets, lengths, key_idx, width, p, out, stream)
+             for p in ("bucketed", "lane1", "lane4")}
+
     def timed(c):
         if c["path"] == "bucketed":
             hh.set_tuning(**dict(saved, **{k: v for k, v in c.items() if k != "path"}))
-        return _time(lambda: hh.hash(keys, data, offsets, lengths, key_idx, width, c["path"],
-                                     out), reps)
+        return _time(calls[c["path"]], reps)
 
     results = []
     try:

@@ -151,12 +151,12 @@ def _msg_args(keys, data, offsets, lengths, key_idx):
             raise ValueError("key_idx and offsets differ in size")
 
 
-def hash(keys: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor, lengths: torch.Tensor,
-         key_idx: Optional[torch.Tensor] = None, width: int = 1, path: str = "auto",
-         out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """HighwayHash of every message; returns (n, width) int64 hash words."""
+def _hash_call(keys, data, offsets, lengths, key_idx, width, path, out):
+    """Checked arguments of hh_hash_path (all but the stream) and the output."""
     if width not in (1, 2, 4):
         raise ValueError("width must be 1, 2 or 4 words")
+    if path not in PATHS:
+        raise ValueError("path must be one of %s" % sorted(PATHS))
     _msg_args(keys, data, offsets, lengths, key_idx)
     n = offsets.numel()
     if out is None:
@@ -165,10 +165,43 @@ def hash(keys: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor, lengths:
         _dev(out, "out", _W64, 2)
         if tuple(out.shape) != (n, width):
             raise ValueError("out must have shape (n, width)")
-    _check(lib().hh_hash_path(PATHS[path], width, _ptr(keys), keys.shape[0], _ptr(key_idx),
-                              _ptr(data), data.numel(), _ptr(offsets), _ptr(lengths), n,
-                              _ptr(out), _stream()))
+    args = (PATHS[path], width, _ptr(keys), keys.shape[0], _ptr(key_idx), _ptr(data),
+            data.numel(), _ptr(offsets), _ptr(lengths), n, _ptr(out))
+    return args, out
+
+
+def hash(keys: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor, lengths: torch.Tensor,
+         key_idx: Optional[torch.Tensor] = None, width: int = 1, path: str = "auto",
+         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """HighwayHash of every message; returns (n, width) int64 hash words."""
+    args, out = _hash_call(keys, data, offsets, lengths, key_idx, width, path, out)
+    _check(lib().hh_hash_path(*args, _stream()))
     return out
+
+
+def prepare(keys: torch.Tensor, data: torch.Tensor, offsets: torch.Tensor,
+            lengths: torch.Tensor, key_idx: Optional[torch.Tensor] = None, width: int = 1,
+            path: str = "auto", out: Optional[torch.Tensor] = None, stream=None):
+    """The hash call of hash(...), with its arguments checked and marshalled
+    once: returns call(), which makes the same hh_hash_path call on `stream`
+    (a torch.cuda.Stream, fixed now; None: the current stream at each call)
+    and returns `out`.  For callers that repeat one call on resident tensors,
+    so that each repetition costs one foreign call instead of the argument
+    checks.  The tensors must stay alive and in place while call() is used."""
+    args, out = _hash_call(keys, data, offsets, lengths, key_idx, width, path, out)
+    fn = lib().hh_hash_path
+    handle = None if stream is None else _vp(stream.cuda_stream)
+    keep = (keys, data, offsets, lengths, key_idx)
+
+    def call():
+        status = fn(*args, handle if handle is not None else _stream())
+        if status != OK:
+            raise HHError(status, status_string(status))
+        return out
+
+    call.out = out
+    call.tensors = keep
+    return call
 
 
 # most messages per hh_hash_noalloc call (HH_NOALLOC_MAX_MSGS in hh.h)

@@ -206,3 +206,27 @@ def test_state_api_equals_one_shot(hh):
     for j in range(n):
         w = int(widths[j])
         assert [int(x) for x in got[j, :w]] == [int(x) for x in want[w][j]], j
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_prepared_call_repeats_the_same_hash(hh, path):
+    # hh.prepare checks and marshals once; each call() makes the same C call
+    # on the given stream and writes the same exact results
+    rng = np.random.default_rng(21)
+    lengths = rng.integers(0, 3000, 900).astype(np.uint64)
+    msgs = [np.frombuffer(rng.bytes(int(L)), np.uint8) for L in lengths]
+    data, offsets, lengths = _pack(msgs, rng)
+    keys = rng.integers(0, 2**64, size=(3, 4), dtype=np.uint64)
+    key_idx = rng.integers(0, 3, lengths.size, dtype=np.uint32)
+    want = oracle_ref(2, keys, key_idx, data, offsets, lengths)
+    k, ki, d, o, L = batch_to_device(keys, key_idx, data, offsets, lengths)
+    stream = torch.cuda.Stream()
+    announce("prepared", path)
+    call = hh.prepare(k, d, o, L, ki, 2, path, None, stream)
+    for _ in range(3):
+        call.out.fill_(-1)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            got = call()
+        stream.synchronize()
+        assert_same(hh.to_u64(got), want, "prepared " + path)
