@@ -21,8 +21,10 @@ Printed as one JSON line:
                kernel's counted VALU lane-ops over that duration.
                roofline.bound names the roof that binds: "critical_path"
                when the longest message's chain covers at least 0.8 of the
-               kernel's time, else "alu" when the VALU fraction exceeds the
-               HBM fraction, else "hbm"; bound_frac is that roof's fraction
+               kernel's time; "latency" when the HBM, VALU and chain
+               fractions all stay below 0.3 (a launch too small to fill the
+               chip); else "alu" when the VALU fraction exceeds the HBM
+               fraction, else "hbm"; bound_frac is that roof's fraction
                (achieved/peak/frac/traffic stay the HBM figures)
   critical_path  the longest message's serial Update chain at the measured
                single-wave Update time
@@ -59,6 +61,8 @@ OUT_BYTES = 8                   # bytes per output word (HighwayHash-64: one wor
 # roofline.bound is "critical_path" when the longest chain covers at least
 # this fraction of the dominant kernel's time
 CRITICAL_BOUND_FRAC = 0.8
+# ... and "latency" when the HBM, VALU and chain fractions all stay below this
+LATENCY_BOUND_FRAC = 0.3
 KEY_BYTES = 32
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 # integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-op per
@@ -158,10 +162,16 @@ def find_profile(kernel: str, workload: str, what: str, workload_name: str, tuni
 def binding_roof(hbm_frac, valu_frac, critical_ms, kernel_ms):
     """(bound, bound_frac): the roof that binds the dominant kernel.  A chain
     that covers at least CRITICAL_BOUND_FRAC of the kernel's time binds it
-    (its fraction: chain floor / kernel time); otherwise the larger of the
-    VALU and HBM fractions names the roof."""
-    if critical_ms and kernel_ms and critical_ms / kernel_ms >= CRITICAL_BOUND_FRAC:
-        return "critical_path", critical_ms / kernel_ms
+    (its fraction: chain floor / kernel time).  When no roof reaches
+    LATENCY_BOUND_FRAC the launch is too small to fill the chip and latency
+    binds ("latency", with the chain's fraction, the nearest floor).
+    Otherwise the larger of the VALU and HBM fractions names the roof."""
+    crit = critical_ms / kernel_ms if critical_ms and kernel_ms else None
+    if crit is not None and crit >= CRITICAL_BOUND_FRAC:
+        return "critical_path", crit
+    fracs = [f for f in (hbm_frac, valu_frac, crit) if f is not None]
+    if fracs and max(fracs) < LATENCY_BOUND_FRAC:
+        return "latency", crit
     if valu_frac is not None and (hbm_frac is None or valu_frac > hbm_frac):
         return "alu", valu_frac
     return "hbm", hbm_frac
@@ -536,7 +546,10 @@ def main(argv=None) -> int:
     if thread_layout:
         t_upd_ns = chain.get("thread_ns_per_update")
     else:
-        t_upd_ns = (chain.get("quad_loop_ring%d_ns_per_update" % ring)
+        # the single-launch quad kernel runs a 12-packet ring, the persistent
+        # kernel the tuned one
+        ring_used = 12 if path == "lane4" else ring
+        t_upd_ns = (chain.get("quad_loop_ring%d_ns_per_update" % ring_used)
                     or chain.get("quad_ns_per_update"))
     n_upd = (longest + 31) // 32 + 4
     critical = None

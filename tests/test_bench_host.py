@@ -117,3 +117,15 @@ def test_summary_file_names_carry_non_default_tuning():
         "hh_long_kernel_lognormal_lane4_min_bytes0_valu.json")
     assert bench.tuning_tag(dict(d, long_ring=96, lane4_min_bytes=0)) == \
         "_lane4_min_bytes0_long_ring96"
+
+
+def test_binding_roof_names_the_roof_that_binds():
+    # the longest chain covering most of the kernel binds it
+    assert bench.binding_roof(0.23, 0.12, 1.13, 1.16) == ("critical_path", 1.13 / 1.16)
+    # VALU above HBM with a short chain: the integer ALUs bind
+    assert bench.binding_roof(0.2, 0.55, 0.001, 0.025) == ("alu", 0.55)
+    # HBM above VALU
+    assert bench.binding_roof(0.6, 0.4, None, 1.0) == ("hbm", 0.6)
+    # nothing near a roof: a launch too small to fill the chip
+    assert bench.binding_roof(0.09, 0.02, 0.0015, 0.0055) == ("latency", 0.0015 / 0.0055)
+    assert bench.binding_roof(None, None, None, None) == ("hbm", None)
