@@ -16,8 +16,9 @@ Printed as one JSON line:
                is measured against), plus single-launch variants
   roofline     the dominant kernel (the persistent long-message kernel on the
                batched path, else the path's one kernel): algorithmic bytes
-               per launch / its mean duration, timed with HIP events around
-               each launch on the launch stream; valu_roofline the same
+               per launch / its mean duration, timed with HIP events on the
+               launch stream (around each persistent launch; around all the
+               back-to-back launches of a one-kernel path); valu_roofline the same
                kernel's counted VALU lane-ops over that duration.
                roofline.bound names the roof that binds: "critical_path"
                when the longest message's chain covers at least 0.8 of the
@@ -444,15 +445,16 @@ def main(argv=None) -> int:
             launches, kernel_ms = hh.timing_collect()
             hh.timing_enable(False)
         else:
-            # one kernel per call: events around each call on this stream
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(args.steps)]
-            for e0, e1 in ev:
-                e0.record()
+            # one kernel per call: one event pair on this stream around the
+            # back-to-back launches (an event pair per launch adds its own
+            # markers to every launch's time)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
                 step()
-                e1.record()
+            e1.record()
             stream.synchronize()
-            launches, kernel_ms = args.steps, sum(e0.elapsed_time(e1) for e0, e1 in ev)
+            launches, kernel_ms = args.steps, e0.elapsed_time(e1)
         stream.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
