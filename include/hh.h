@@ -24,9 +24,9 @@
  *   - Message j is data[offsets[j] .. offsets[j] + lengths[j]), bytes at any
  *     alignment and of any 64-bit length (offsets and messages beyond 4 GiB
  *     included); offsets[j] + lengths[j] <= data_bytes is the caller's
- *     contract.  The kernels never read outside [data, data + data_bytes)
- *     rounded out to whole 4-byte words: a message that violates the contract
- *     is clamped to the buffer and hashed truncated, it never faults.
+ *     contract.  The kernels never read outside [data, data + data_bytes):
+ *     a message that violates the contract is clamped to the buffer and
+ *     hashed truncated, it never faults.
  *   - key_idx[j] selects message j's key; NULL means key 0 for every message.
  *     An index >= n_keys is clamped to n_keys - 1.
  *   - Outputs are uint64 words, message-major, lane 0 first:

@@ -246,10 +246,9 @@ __device__ __forceinline__ u64 finalize1(State1& s) {
 // serves byte-aligned dword loads (the HSA unaligned access mode the compiler
 // itself relies on), so a lane's 8 packet bytes are one global_load_dwordx2.
 // The 1..3 bytes at the very end of a message come from the unaligned dword
-// that ends at its last byte; only a message shorter than 4 bytes is read as
-// the aligned dwords that hold it, which leave the caller's buffer by at most
-// the rest of its last dword (never another page).  Pointers keep their
-// provenance (no integer round trip) so that the loads stay global_load.
+// that ends at its last byte; a message shorter than 4 bytes is read byte by
+// byte.  No load leaves the message's bytes.  Pointers keep their provenance
+// (no integer round trip) so that the loads stay global_load.
 
 typedef u64 u64_any_align __attribute__((aligned(1)));
 typedef u32 u32_any_align __attribute__((aligned(1)));
@@ -257,17 +256,14 @@ typedef u32 u32_any_align __attribute__((aligned(1)));
 __device__ __forceinline__ u64 load_le64(const u8* p) { return *(const u64_any_align*)p; }
 __device__ __forceinline__ u32 load_le32(const u8* p) { return *(const u32_any_align*)p; }
 
-__device__ __forceinline__ u32 misalignment(const u8* p) { return (u32)((uintptr_t)p & 3u); }
-
-// Little-endian word of the n (0..4) bytes at p; bytes past n read as 0.
+// Little-endian word of the n (0..3) bytes at p, read one byte at a time
+// (the bytes may end at the buffer's last byte); bytes past n read as 0.
 __device__ __forceinline__ u32 load_partial_le32(const u8* p, u32 n) {
-    if (n == 0) return 0u;
-    const u32 sh = misalignment(p);
-    const u32* d = (const u32*)(p - sh);
-    const u32 d0 = d[0];
-    const u32 d1 = (sh + n > 4u) ? d[1] : 0u;
-    const u32 w = align_bytes(d1, d0, sh);
-    return n >= 4u ? w : (w & ((1u << (8u * n)) - 1u));
+    u32 w = 0u;
+    if (n > 0u) w = p[0];
+    if (n > 1u) w |= (u32)p[1] << 8;
+    if (n > 2u) w |= (u32)p[2] << 16;
+    return w;
 }
 
 // Sec. 4.5 padded remainder packet: the dword that takes the last r%4 tail
