@@ -23,7 +23,7 @@ Printed as one JSON line:
                roofline.bound names the roof that binds: "critical_path"
                when the longest message's chain covers at least 0.8 of the
                kernel's time; "latency" when the HBM, VALU and chain
-               fractions all stay below 0.3 (a launch too small to fill the
+               fractions all stay below 0.5 (a launch too small to fill the
                chip); else "alu" when the VALU fraction exceeds the HBM
                fraction, else "hbm"; bound_frac is that roof's fraction
                (achieved/peak/frac/traffic stay the HBM figures)
@@ -63,7 +63,7 @@ OUT_BYTES = 8                   # bytes per output word (HighwayHash-64: one wor
 # this fraction of the dominant kernel's time
 CRITICAL_BOUND_FRAC = 0.8
 # ... and "latency" when the HBM, VALU and chain fractions all stay below this
-LATENCY_BOUND_FRAC = 0.3
+LATENCY_BOUND_FRAC = 0.5
 KEY_BYTES = 32
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 # integer VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-op per

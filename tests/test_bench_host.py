@@ -128,4 +128,5 @@ def test_binding_roof_names_the_roof_that_binds():
     assert bench.binding_roof(0.6, 0.4, None, 1.0) == ("hbm", 0.6)
     # nothing near a roof: a launch too small to fill the chip
     assert bench.binding_roof(0.09, 0.02, 0.0015, 0.0055) == ("latency", 0.0015 / 0.0055)
+    assert bench.binding_roof(0.12, 0.09, 0.0015, 0.0043) == ("latency", 0.0015 / 0.0043)
     assert bench.binding_roof(None, None, None, None) == ("hbm", None)
