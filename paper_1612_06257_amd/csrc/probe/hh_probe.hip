@@ -1,7 +1,7 @@
 // hh_probe.hip -- measurement kernels for the roofline figures (libhh_probe.so).
 //
 //   hh_probe_chain      cycles per Update of one wave running a long chain of
-//                       Updates on register data (quad or thread layout),
+//                       Updates on register data (quad, pair or thread layout),
 //                       with n_waves waves launched and an optional s_setprio
 //                       for the first `prio_waves` of them.
 //   hh_probe_op_rate    aggregate rate of one VALU instruction kind.
@@ -16,7 +16,33 @@
 
 namespace hh {
 
-template <bool QUAD>
+// Pair layout (two threads per message, thread h holds lanes 2h and 2h+1):
+// a lane pair is exactly a ZipperMerge pair, so the Update needs no
+// exchange; only Permute (finalization) would take the other thread's v0.
+// Here for the chain measurement only.
+struct State2 {
+    u64 v0[2], v1[2], mul0[2], mul1[2];
+};
+
+__device__ __forceinline__ void update2(State2& s, const u64 p[2]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        s.v1[i] += p[i] + s.mul0[i];
+        s.mul0[i] ^= mul_lo_hi(s.v1[i], s.v0[i]);
+        s.v0[i] += s.mul1[i];
+        s.mul1[i] ^= mul_lo_hi(s.v0[i], s.v1[i]);
+    }
+    u64 z[2];
+    zipper_pair(s.v1[0], s.v1[1], z[0], z[1]);
+    s.v0[0] += z[0];
+    s.v0[1] += z[1];
+    zipper_pair(s.v0[0], s.v0[1], z[0], z[1]);
+    s.v1[0] += z[0];
+    s.v1[1] += z[1];
+}
+
+// LAYOUT 0: thread (one thread per message), 1: quad, 2: pair.
+template <int LAYOUT>
 __global__ __launch_bounds__(64) void hh_probe_chain_kernel(u32 n_updates, u32 prio_waves,
                                                             u64* __restrict__ cycles,
                                                             u64* __restrict__ sink) {
@@ -25,7 +51,23 @@ __global__ __launch_bounds__(64) void hh_probe_chain_kernel(u32 n_updates, u32 p
     u64 x = 0x9e3779b97f4a7c15ull * (lane + 1) + blockIdx.x;
     u64 acc = 0;
     const u64 t0 = __builtin_amdgcn_s_memtime();
-    if (QUAD) {
+    if (LAYOUT == 2) {
+        const int h = (int)(lane & 1u);
+        State2 s;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = 2 * h + i;
+            s.mul0[i] = init0(q);
+            s.mul1[i] = init1(q);
+            s.v0[i] = (x + i) ^ s.mul0[i];
+            s.v1[i] = rot32(x + i) ^ s.mul1[i];
+        }
+        for (u32 t = 0; t < n_updates; ++t) {
+            const u64 p[2] = {x + t, x ^ t};
+            update2(s, p);
+        }
+        acc = s.v0[0] ^ s.v1[1] ^ s.mul0[0] ^ s.mul1[1];
+    } else if (LAYOUT == 1) {
         State1 s;
         reset1(s, x, lane & 3);
         for (u32 t = 0; t < n_updates; ++t) update1(s, x + t);
@@ -117,16 +159,20 @@ using namespace hh;
 extern "C" {
 
 // cycles[w] = s_memtime cycles of wave w for n_updates Updates; sink needs
-// 64 * n_waves words.
-int hh_probe_chain(int quad, u32 n_updates, u32 n_waves, u32 prio_waves, u64* cycles, u64* sink,
-                   void* stream) {
-    if (n_waves == 0 || !cycles || !sink) return 1;
-    if (quad)
-        hipLaunchKernelGGL(hh_probe_chain_kernel<true>, dim3(n_waves), dim3(64), 0,
-                           (hipStream_t)stream, n_updates, prio_waves, cycles, sink);
+// 64 * n_waves words.  layout: 0 thread, 1 quad, 2 pair.
+int hh_probe_chain(int layout, u32 n_updates, u32 n_waves, u32 prio_waves, u64* cycles,
+                   u64* sink, void* stream) {
+    if (n_waves == 0 || !cycles || !sink || layout < 0 || layout > 2) return 1;
+    hipStream_t st = (hipStream_t)stream;
+    if (layout == 1)
+        hipLaunchKernelGGL(hh_probe_chain_kernel<1>, dim3(n_waves), dim3(64), 0, st, n_updates,
+                           prio_waves, cycles, sink);
+    else if (layout == 2)
+        hipLaunchKernelGGL(hh_probe_chain_kernel<2>, dim3(n_waves), dim3(64), 0, st, n_updates,
+                           prio_waves, cycles, sink);
     else
-        hipLaunchKernelGGL(hh_probe_chain_kernel<false>, dim3(n_waves), dim3(64), 0,
-                           (hipStream_t)stream, n_updates, prio_waves, cycles, sink);
+        hipLaunchKernelGGL(hh_probe_chain_kernel<0>, dim3(n_waves), dim3(64), 0, st, n_updates,
+                           prio_waves, cycles, sink);
     return hipGetLastError() == hipSuccess ? 0 : 4;
 }
 

@@ -3,9 +3,10 @@
     python -m paper_1612_06257_amd.microbench [--json out.jsonl]
 
 * chain:   cycles per Update of one wave running a long serial chain of
-           Updates on register data, in the four-threads-per-message (quad)
-           and one-thread-per-message layouts, alone and with other waves
-           sharing the chip, with and without s_setprio on the measured waves.
+           Updates on register data, in the four-threads-per-message (quad),
+           two-threads-per-message (pair) and one-thread-per-message layouts,
+           alone and with other waves sharing the chip, with and without
+           s_setprio on the measured waves.
            This is the per-message critical path: a message is one serial
            chain of ceil(L/32)+4 Updates.
 * op rate: aggregate rate of each VALU instruction the Update uses, in
@@ -66,18 +67,21 @@ def _time(fn, reps=5):
     return float(np.median(ts))
 
 
-def chain(L, quad: bool, n_updates: int, n_waves: int, prio_waves: int = 0):
+LAYOUTS = {"thread": 0, "quad": 1, "pair": 2}
+
+
+def chain(L, layout: str, n_updates: int, n_waves: int, prio_waves: int = 0):
     cycles = torch.zeros(n_waves, dtype=torch.int64, device="cuda")
     sink = torch.zeros(64 * n_waves, dtype=torch.int64, device="cuda")
 
     def go():
-        rc = L.hh_probe_chain(int(quad), n_updates, n_waves, prio_waves, _vp(cycles.data_ptr()),
-                              _vp(sink.data_ptr()), _stream())
+        rc = L.hh_probe_chain(LAYOUTS[layout], n_updates, n_waves, prio_waves,
+                              _vp(cycles.data_ptr()), _vp(sink.data_ptr()), _stream())
         assert rc == 0, rc
 
     ms = _time(go, reps=3)
     c = cycles.cpu().numpy().astype(np.float64) / n_updates
-    rec = {"kind": "chain", "layout": "quad" if quad else "thread", "n_waves": n_waves,
+    rec = {"kind": "chain", "layout": layout, "n_waves": n_waves,
            "prio_waves": prio_waves, "n_updates": n_updates, "kernel_ms": ms,
            "cycles_per_update_median": float(np.median(c)),
            "cycles_per_update_max": float(c.max()), "cycles_per_update_min": float(c.min())}
@@ -177,12 +181,12 @@ def main(argv=None):
         _write(args, recs, argv)
         return
     n_up = 20000
-    for quad in (True, False):
+    for layout in ("quad", "thread", "pair"):
         for n_waves in (1, cus, 4 * cus, 8 * cus, 16 * cus):
-            recs.append(chain(L, quad, n_up, n_waves))
+            recs.append(chain(L, layout, n_up, n_waves))
             print(json.dumps(recs[-1]), flush=True)
         # priority: the first cus waves raise their priority, 16/CU in total
-        recs.append(chain(L, quad, n_up, 16 * cus, prio_waves=cus))
+        recs.append(chain(L, layout, n_up, 16 * cus, prio_waves=cus))
         print(json.dumps(recs[-1]), flush=True)
     buf = None
     for ring in (12, 24, 36, 48, 72, 96):
