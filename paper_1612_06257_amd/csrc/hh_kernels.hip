@@ -235,8 +235,14 @@ hh_status launch_thread(const HashArgs& a, u64 uniform_length, hipStream_t st) {
     return launch_thread_ring<kThreadRing>(a, uniform_length, st);
 }
 
+// Quad-layout launches use one-wave workgroups: the dispatcher spreads them
+// over the CUs, so fewer long chains share a CU's load path (four waves of
+// one workgroup on a CU ran each chain about 10% slower; serving saturation
+// 179-182 -> 201-204 GB/s with the state kernels launched this way).
+constexpr unsigned kQuadBlock = 64;
+
 hh_status launch_quad(const HashArgs& a, hipStream_t st) {
-    const unsigned block = 256;
+    const unsigned block = kQuadBlock;
     const unsigned grid = grid_for(4 * a.n, block);
     switch (a.width) {
         case 1: hipLaunchKernelGGL(hh_quad_kernel<1>, dim3(grid), dim3(block), 0, st, a.keys,
@@ -291,7 +297,7 @@ hh_status launch_state_step(int mode, u64* states, u64 n_states, const u32* stat
                             const u8* data, u64 data_bytes, const u64* offsets,
                             const u64* lengths, const u8* width_words, u64* out, u64 out_words,
                             const u64* out_offsets, u64 n, hipStream_t st) {
-    const unsigned block = 256;
+    const unsigned block = kQuadBlock;
     const unsigned grid = grid_for(4 * n, block);
 #define HH_STEP(M)                                                                          \
     hipLaunchKernelGGL(hh_state_step_kernel<M>, dim3(grid), dim3(block), 0, st, states,    \
