@@ -16,6 +16,8 @@
 // The bucketed planner and persistent kernel live in hh_batched.hip, the
 // avalanche statistics in hh_stats.hip.
 
+#include <atomic>
+
 #include "hh_device.hpp"
 #include "hh_internal.hpp"
 #include "hh_msg.hpp"
@@ -67,12 +69,85 @@ __global__ __launch_bounds__(256) void hh_quad_kernel(
 // message has no whole packet; its remainder packet (Sec. 4.5, r = 8) is the
 // counter in lane 0 and zeros, so nothing is read but the key.
 
+// The part of an 8-byte message's hash that does not depend on the counter,
+// for one key (Sec. 4.4, 4.5, 4.2): Reset; the size injection and v1
+// rotation of the remainder step (r = 8); the absorb of the padded packet's
+// zero words into lanes 1..3; the ZipperMerges of lane pair (2,3), whose
+// inputs are then complete.  Lane 0 keeps v1 + mul0 (`a0`) and v0 as the
+// absorb reads it (`v0_in`), and v0 + mul1 in the state, all independent of
+// the counter.
+struct PrfKey {
+    State4 s;
+    u64 a0, v0_in;
+};
+
+__device__ __forceinline__ void prf_prepare(const u64 key[4], PrfKey& k) {
+    State4& s = k.s;
+    reset4(s, key);
+    const u64 inject = (8ull << 32) + 8ull;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        s.v0[i] += inject;
+        s.v1[i] = rotl_halves(s.v1[i], 8u);
+    }
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+        s.v1[i] += s.mul0[i];  // + the packet word, 0
+        s.mul0[i] ^= mul_lo_hi(s.v1[i], s.v0[i]);
+        s.v0[i] += s.mul1[i];
+        s.mul1[i] ^= mul_lo_hi(s.v0[i], s.v1[i]);
+    }
+    k.a0 = s.v1[0] + s.mul0[0];
+    k.v0_in = s.v0[0];
+    s.v0[0] += s.mul1[0];
+    u64 z2, z3;
+    zipper_pair(s.v1[2], s.v1[3], z2, z3);
+    s.v0[2] += z2;
+    s.v0[3] += z3;
+    zipper_pair(s.v0[2], s.v0[3], z2, z3);
+    s.v1[2] += z2;
+    s.v1[3] += z3;
+}
+
+// The rest of the remainder Update for counter c (lane 0 absorbs c, then the
+// lane pair (0,1) is merged), then the finalization.
+__device__ __forceinline__ void prf_finish(const PrfKey& k, u64 c, u64 sum[4]) {
+    State4 s = k.s;
+    s.v1[0] = k.a0 + c;
+    s.mul0[0] ^= mul_lo_hi(s.v1[0], k.v0_in);
+    s.mul1[0] ^= mul_lo_hi(s.v0[0], s.v1[0]);
+    u64 z0, z1;
+    zipper_pair(s.v1[0], s.v1[1], z0, z1);
+    s.v0[0] += z0;
+    s.v0[1] += z1;
+    zipper_pair(s.v0[0], s.v0[1], z0, z1);
+    s.v1[0] += z0;
+    s.v1[1] += z1;
+    finalize4(s, sum);
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void hh_prf_kernel(const u64* __restrict__ keys, u32 n_keys,
-                                                     u64 counter_base, u64 n,
+                                                     u64 counter_base, u64 n, u64 stride,
                                                      u64* __restrict__ out) {
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    for (u64 j = (u64)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+    const u64 j0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j0 >= stride) return;
+    if (stride % n_keys == 0) {
+        // every counter of this thread takes the same key: its
+        // counter-independent part is computed once
+        const u64* kp = keys + 4 * ((counter_base + j0) % n_keys);
+        const u64 key[4] = {kp[0], kp[1], kp[2], kp[3]};
+        PrfKey pk;
+        prf_prepare(key, pk);
+        for (u64 j = j0; j < n; j += stride) {
+            u64 sum[4];
+            prf_finish(pk, counter_base + j, sum);
+#pragma unroll
+            for (int i = 0; i < W; ++i) out[(u64)W * j + i] = sum[i];
+        }
+        return;
+    }
+    for (u64 j = j0; j < n; j += stride) {
         const u64 c = counter_base + j;
         const u64* kp = keys + 4 * (c % n_keys);
         const u64 key[4] = {kp[0], kp[1], kp[2], kp[3]};
@@ -258,17 +333,52 @@ hh_status launch_quad(const HashArgs& a, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
 }
 
+// Counter-mode PRF launch: a persistent grid whose thread count (the loop
+// stride) is a multiple of n_keys when that fits, so that each thread keeps
+// one key for all its counters.
+template <int W>
+u32 prf_resident_threads(unsigned block) {
+    static std::atomic<u32> per_cu{0};
+    u32 b = per_cu.load(std::memory_order_relaxed);
+    if (!b) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, hh_prf_kernel<W>, (int)block, 0) !=
+                hipSuccess ||
+            nb < 1) {
+            (void)hipGetLastError();
+            nb = 1;
+        }
+        b = (u32)nb;
+        per_cu.store(b, std::memory_order_relaxed);
+    }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    return (u32)cus * b * block;
+}
+
+template <int W>
+void launch_prf_w(const u64* keys, u32 n_keys, u64 counter_base, u64 n, u64* out,
+                  hipStream_t st) {
+    const unsigned block = 256;
+    u64 stride = prf_resident_threads<W>(block);
+    if (stride >= n_keys) stride = stride / n_keys * n_keys;
+    if (stride > n) stride = n;
+    const unsigned grid = grid_for(stride, block);
+    hipLaunchKernelGGL(hh_prf_kernel<W>, dim3(grid), dim3(block), 0, st, keys, n_keys,
+                       counter_base, n, stride, out);
+}
+
 hh_status launch_prf(u32 width, const u64* keys, u32 n_keys, u64 counter_base, u64 n, u64* out,
                      hipStream_t st) {
-    const unsigned block = 256;
-    const unsigned grid = grid_for(n, block);
     switch (width) {
-        case 1: hipLaunchKernelGGL(hh_prf_kernel<1>, dim3(grid), dim3(block), 0, st, keys, n_keys,
-                                   counter_base, n, out); break;
-        case 2: hipLaunchKernelGGL(hh_prf_kernel<2>, dim3(grid), dim3(block), 0, st, keys, n_keys,
-                                   counter_base, n, out); break;
-        default: hipLaunchKernelGGL(hh_prf_kernel<4>, dim3(grid), dim3(block), 0, st, keys,
-                                    n_keys, counter_base, n, out); break;
+        case 1: launch_prf_w<1>(keys, n_keys, counter_base, n, out, st); break;
+        case 2: launch_prf_w<2>(keys, n_keys, counter_base, n, out, st); break;
+        default: launch_prf_w<4>(keys, n_keys, counter_base, n, out, st); break;
     }
     return hipGetLastError() == hipSuccess ? HH_OK : HH_ERR_LAUNCH;
 }

@@ -79,3 +79,31 @@ def test_prf_top16_histogram_chi_square(prf_out):
     chi2 = float(((counts - expected) ** 2 / expected).sum())
     p = stats.chi2.sf(chi2, 65535)
     assert 1e-6 < p < 1 - 1e-6, (chi2, p)
+
+
+@pytest.mark.parametrize("n_keys,n,base", [(37, 3_000_001, 5), (1, 1_000_003, 2**64 - 1000),
+                                           (1024, 1_500_000, 77), (700_001, 2_000_000, 0)])
+def test_prf_every_launch_shape(hh, n_keys, n, base):
+    # the grid keeps one key per thread when its thread count can be made a
+    # multiple of n_keys (37, 1, 1024 here), else takes the key per counter
+    # (700001 keys, more than the resident threads); both against the batch
+    # path on every counter and the oracle on samples
+    rng = np.random.default_rng(62)
+    keys = rng.integers(0, 2**64, size=(n_keys, 4), dtype=np.uint64)
+    kt = torch.from_numpy(keys).view(torch.int64).cuda()
+    announce("prf shape", n_keys, n, base)
+    for width in (1, 4):
+        got = hh.prf(kt, n, base, width)
+        c = (np.uint64(base) + np.arange(n, dtype=np.uint64))   # wraps mod 2^64
+        ref = hh.hash(kt, torch.from_numpy(c.view(np.uint8)).cuda(),
+                      torch.arange(0, 8 * n, 8, dtype=torch.int64, device="cuda"),
+                      torch.full((n,), 8, dtype=torch.int64, device="cuda"),
+                      torch.from_numpy((c % np.uint64(n_keys)).astype(np.uint32)).view(
+                          torch.int32).cuda(), width)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, got), (n_keys, n, width)
+        g = hh.to_u64(got)
+        for j in list(rng.integers(0, n, 20)) + [0, n - 1]:
+            cj = int(c[j])
+            msg = np.frombuffer(cj.to_bytes(8, "little"), np.uint8)
+            assert [int(x) for x in g[j]] == oracle.hash_words(keys[cj % n_keys], msg, width)
