@@ -31,6 +31,7 @@ import bisect
 import collections
 import concurrent.futures
 import dataclasses
+import gc
 import json
 import sys
 import time
@@ -439,7 +440,22 @@ class Server:
         admission takes the longest run of queued requests that the free
         slots, the budget and one contiguous arena range can hold, and a
         harvest retires a finished iteration's requests at once.  The Request
-        objects are filled in after the run."""
+        objects are filled in after the run.
+
+        Python's cyclic garbage collector is off while the loop runs (and
+        back in its previous state after): a full pass over a process that
+        holds a few hundred thousand objects stops the loop for about 40 ms,
+        which held every request in flight that long in some runs.  The loop
+        makes no reference cycles of its own."""
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests)
+        finally:
+            if was_enabled:
+                gc.enable()
+
+    def _run(self, requests: List[Request]) -> dict:
         order = sorted(range(len(requests)), key=lambda i: requests[i].arrival)
         reqs = [requests[i] for i in order]
         n_total = len(reqs)

@@ -137,3 +137,30 @@ def test_long_lane_results_equal_one_shot():
     for r in reqs:
         msg = tr.data[r.src:r.src + r.length]
         assert r.result == tuple(oracle.hash_words(tr.keys[r.key_idx], msg, r.width)), r.rid
+
+
+def test_collector_off_during_the_loop_and_restored():
+    # the loop runs with Python's cyclic collector off (a full pass can stop
+    # it for tens of milliseconds) and leaves the collector as it found it
+    import gc
+
+    class Recording(CpuBackend):
+        def launch(self, *a, **k):
+            self.gc_states.add(gc.isenabled())
+            return super().launch(*a, **k)
+
+    tr = _trace(60, 2000.0, hi=3000, seed=41)
+    for enabled in (True, False):
+        (gc.enable if enabled else gc.disable)()
+        try:
+            clock = VirtualClock()
+            reqs = serve.requests_from_trace(tr)
+            be = Recording(tr.keys, tr.data, 1 << 16, 64, clock)
+            be.gc_states = set()
+            srv = serve.Server(be, budget_bytes=1 << 16, chunk_bytes=64, clock=clock,
+                               sleep=clock.sleep)
+            assert srv.run(reqs)["completed"] == len(reqs)
+            assert be.gc_states == {False}
+            assert gc.isenabled() == enabled
+        finally:
+            gc.enable()
