@@ -45,6 +45,7 @@ Printed as one JSON line:
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -430,6 +431,9 @@ def main(argv=None) -> int:
         else:
             call()
 
+    # no cyclic-collector pass inside the timed launches (a full pass stops
+    # the host for tens of milliseconds and the GPU would run dry)
+    gc.disable()
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             step()
@@ -461,6 +465,7 @@ def main(argv=None) -> int:
             step()
         stream.synchronize()
         sec = time.perf_counter() - t0
+    gc.enable()
     ms_per_step = sec * 1e3 / args.steps
     value = b.total_bytes * args.steps / sec / 1e9
     gpu_hash = hh.to_u64(out).copy()
@@ -523,12 +528,14 @@ def main(argv=None) -> int:
                 with torch.cuda.stream(s_):
                     hh.hash(k, d, o, L, ki, width, path, o_)
             torch.cuda.synchronize()
+            gc.disable()
             t0 = time.perf_counter()
             for i in range(args.steps):
                 with torch.cuda.stream(streams[i % n_streams]):
                     hh.hash(k, d, o, L, ki, width, path, outs[i % n_streams])
             torch.cuda.synchronize()
             psec = time.perf_counter() - t0
+            gc.enable()
             exact = all(np.array_equal(hh.to_u64(x), gpu_hash) for x in outs)
             pipelined.append({"streams": n_streams, "value": b.total_bytes * args.steps / psec / 1e9,
                               "unit": "GB/s", "ms_per_batch": psec * 1e3 / args.steps,
