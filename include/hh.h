@@ -57,7 +57,8 @@ typedef enum {
     HH_ERR_INVALID_ARG = 1,
     HH_ERR_UNSUPPORTED_DEVICE = 2,
     HH_ERR_OUT_OF_MEMORY = 3,
-    HH_ERR_LAUNCH = 4
+    HH_ERR_LAUNCH = 4,
+    HH_ERR_BUSY = 5
 } hh_status;
 
 /* Human-readable text for a status code (static storage, never NULL). */
@@ -209,6 +210,65 @@ hh_status hh_state_step(uint64_t* states, uint64_t n_states, const uint32_t* sta
 hh_status hh_copy_segments(uint8_t* dst, uint64_t dst_bytes, const uint8_t* src,
                            uint64_t src_bytes, const uint64_t* src_offs, const uint64_t* dst_offs,
                            const uint64_t* lens, uint64_t n, uint64_t max_len, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Continuous hashing of long messages (serving): a persistent kernel takes
+ * groups of messages from a queue in host memory while it runs and hashes
+ * each message whole (Sec. 4.2-4.5, four threads per message), so that a
+ * message submitted while others are being hashed starts at once on an idle
+ * wave instead of waiting for the next launch.  Results reach host memory
+ * directly.  One feed serves one caller thread at a time (calls on one feed
+ * are serialised by a lock).
+ *
+ * hh_feed_open: keys (device, n_keys x 4 words) and the byte buffer
+ * data[0 .. data_bytes) (device) are fixed for the feed's life; the caller
+ * keeps them alive and unmodified where submitted messages lie until their
+ * results are seen.  `slots` result rows (1 .. HH_FEED_MAX_SLOTS) live in
+ * pinned host memory owned by the feed.  `waves` (2 .. HH_FEED_MAX_WAVES)
+ * one-wave workgroups are launched on `stream` (which then carries nothing
+ * else while the feed is open): one dispatcher and waves - 1 hashing waves,
+ * each hashing one group at a time.  Each launch ends by itself after
+ * max_ms (1 .. HH_FEED_MAX_MS) milliseconds; hh_feed_submit and hh_feed_poll
+ * launch again while submitted groups wait.  Allocates host and device
+ * memory (HH_ERR_OUT_OF_MEMORY). */
+#define HH_FEED_GROUP 16
+#define HH_FEED_MAX_SLOTS 65536u
+#define HH_FEED_MAX_WAVES 4096u
+#define HH_FEED_MAX_MS 60000u
+typedef struct hh_feed hh_feed;
+hh_status hh_feed_open(const uint64_t* keys, uint32_t n_keys, const uint8_t* data,
+                       uint64_t data_bytes, uint32_t slots, uint32_t waves, uint32_t max_ms,
+                       void* stream, hh_feed** feed);
+
+/* Queue one group of n (1 .. HH_FEED_GROUP) messages; the arrays are HOST
+ * arrays of n entries, read before the call returns.  Message i is
+ * data[offsets[i] .. + lengths[i]) (clamped to data_bytes) under key
+ * key_idx[i] (NULL: key 0; clamped to n_keys - 1), and its width_words[i]
+ * (1, 2 or 4) hash words go to result row slot[i] (< slots).  The messages of
+ * a group are hashed side by side and their results appear when the longest
+ * is done, so a group should hold messages of similar length.  *first_ticket
+ * receives the ticket of message 0; message i has ticket first + i (tickets
+ * start at 1 and never repeat in a feed).  A slot must not be submitted
+ * again until its result has been seen.  HH_ERR_BUSY: the queue holds
+ * `slots` groups that no wave has taken yet; submit again later. */
+hh_status hh_feed_submit(hh_feed* feed, uint32_t n, const uint64_t* offsets,
+                         const uint64_t* lengths, const uint32_t* key_idx,
+                         const uint8_t* width_words, const uint32_t* slot,
+                         uint64_t* first_ticket);
+
+/* Launch the kernel again if its last launch has ended while submitted
+ * groups wait.  Call it from the loop that watches the results. */
+hh_status hh_feed_poll(hh_feed* feed);
+
+/* Result rows (host memory, 5 words per slot): row s holds the hash words of
+ * the message last hashed for slot s, then that message's ticket.  The
+ * words of a message are in place once its ticket is: read the ticket, then
+ * the words.  Valid until hh_feed_close; NULL for a null feed. */
+const volatile uint64_t* hh_feed_results(const hh_feed* feed);
+
+/* Stop the kernel (it finishes the groups it has taken), wait for it and
+ * free the feed. */
+hh_status hh_feed_close(hh_feed* feed);
 
 /* ---------------------------------------------------------------------------
  * Avalanche statistics (the strengthened avalanche test of Sec. 6.1 and the

@@ -81,6 +81,7 @@ const char* hh_status_string(hh_status status) {
         case HH_ERR_UNSUPPORTED_DEVICE: return "no gfx950 device is current";
         case HH_ERR_OUT_OF_MEMORY: return "out of device memory";
         case HH_ERR_LAUNCH: return "kernel launch failed";
+        case HH_ERR_BUSY: return "queue full, try again later";
     }
     return "unknown status";
 }

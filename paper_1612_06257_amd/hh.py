@@ -19,12 +19,13 @@ import ctypes
 import os
 from typing import Optional, List
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhh.so")
 
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_DEVICE, ERR_OUT_OF_MEMORY, ERR_LAUNCH = range(5)
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_DEVICE, ERR_OUT_OF_MEMORY, ERR_LAUNCH, ERR_BUSY = range(6)
 PATHS = {"auto": 0, "lane1": 1, "lane4": 2, "bucketed": 3}
 STATE_WORDS = 16
 
@@ -97,6 +98,16 @@ def lib() -> ctypes.CDLL:
         L.hh_timing_collect.argtypes = [ctypes.POINTER(ctypes.c_uint32),
                                         ctypes.POINTER(ctypes.c_double)]
         L.hh_timing_collect.restype = ctypes.c_int
+        L.hh_feed_open.argtypes = [_vp, _u32, _vp, _u64, _u32, _u32, _u32, _vp, ctypes.POINTER(_vp)]
+        L.hh_feed_open.restype = ctypes.c_int
+        L.hh_feed_submit.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_u64)]
+        L.hh_feed_submit.restype = ctypes.c_int
+        L.hh_feed_poll.argtypes = [_vp]
+        L.hh_feed_poll.restype = ctypes.c_int
+        L.hh_feed_results.argtypes = [_vp]
+        L.hh_feed_results.restype = _vp
+        L.hh_feed_close.argtypes = [_vp]
+        L.hh_feed_close.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -450,6 +461,70 @@ def set_tuning(**kw) -> None:
 def release() -> None:
     """Free the library's per-stream workspaces and cached graphs (no call may be in flight)."""
     _check(lib().hh_release())
+
+
+# messages per hh_feed_submit group (HH_FEED_GROUP in hh.h)
+FEED_GROUP = 16
+
+
+class Feed:
+    """hh_feed_*: a persistent kernel that hashes long messages as they are
+    submitted (see hh.h).  `keys` (n_keys x 4, device) and `data` (uint8,
+    device) stay fixed and alive while the feed is open.  rows is a
+    (slots, 5) uint64 view of the feed's host result rows: four hash words,
+    then the ticket of the message they belong to."""
+
+    def __init__(self, keys: torch.Tensor, data: torch.Tensor, slots: int, waves: int = 256,
+                 max_ms: int = 2000, stream=None):
+        _dev(keys, "keys", _W64, 2)
+        if keys.shape[1] != 4 or keys.shape[0] < 1:
+            raise ValueError("keys must have shape (n_keys >= 1, 4)")
+        _dev(data, "data", (torch.uint8,), 1)
+        self.keys, self.data, self.slots = keys, data, int(slots)
+        h = _vp()
+        st = _vp(stream.cuda_stream) if stream is not None else _stream()
+        _check(lib().hh_feed_open(_ptr(keys), keys.shape[0], _ptr(data), data.numel(),
+                                  self.slots, int(waves), int(max_ms), st, ctypes.byref(h)))
+        self._h = h
+        base = lib().hh_feed_results(h)
+        self.rows = np.ctypeslib.as_array(
+            (ctypes.c_uint64 * (5 * self.slots)).from_address(base)).reshape(self.slots, 5)
+
+    def submit(self, offsets, lengths, key_idx, widths, slots) -> int:
+        """Queue one group (at most FEED_GROUP messages; host arrays); returns
+        the first message's ticket (message i: ticket + i), or 0 when the
+        queue is full (submit again later)."""
+        o = np.ascontiguousarray(offsets, np.uint64)
+        L = np.ascontiguousarray(lengths, np.uint64)
+        k = np.ascontiguousarray(key_idx, np.uint32)
+        w = np.ascontiguousarray(widths, np.uint8)
+        s = np.ascontiguousarray(slots, np.uint32)
+        n = o.size
+        if not (L.size == k.size == w.size == s.size == n):
+            raise ValueError("group arrays must have equal lengths")
+        t = _u64()
+        st = lib().hh_feed_submit(self._h, n, o.ctypes.data, L.ctypes.data, k.ctypes.data,
+                                  w.ctypes.data, s.ctypes.data, ctypes.byref(t))
+        if st == ERR_BUSY:
+            return 0
+        _check(st)
+        return int(t.value)
+
+    def poll(self) -> None:
+        """Relaunch the kernel if it has ended while submitted groups wait."""
+        _check(lib().hh_feed_poll(self._h))
+
+    def close(self) -> None:
+        if self._h is not None:
+            h, self._h = self._h, None
+            self.rows = None
+            _check(lib().hh_feed_close(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pinned_device_pointer(t: torch.Tensor) -> int:

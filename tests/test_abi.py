@@ -21,7 +21,8 @@ def _hh():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(hh_[a-z0-9_]+)\s*\(",
+    names = re.findall(r"^\s*(?:const\s+)?(?:volatile\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*"
+                       r"(hh_[a-z0-9_]+)\s*\(",
                        text, flags=re.M)
     return sorted(set(names))
 
@@ -29,7 +30,9 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("hh_hash64", "hh_hash128", "hh_hash256", "hh_hash64_uniform", "hh_hash_path",
-                 "hh_state_init", "hh_state_update", "hh_state_final", "hh_status_string"):
+                 "hh_state_init", "hh_state_update", "hh_state_final", "hh_status_string",
+                 "hh_feed_open", "hh_feed_submit", "hh_feed_poll", "hh_feed_results",
+                 "hh_feed_close"):
         assert want in names
 
 
@@ -41,8 +44,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     hh = _hh()
-    for s in range(5):
-        assert hh.status_string(s)
+    for s in range(6):
+        assert hh.status_string(s) != "unknown status"
     assert hh.status_string(0) == "ok"
     assert hh.lib().hh_version() >= 100
 
@@ -78,6 +81,24 @@ def test_invalid_arguments_rejected_without_device():
     assert L.hh_hash_noalloc(1, dummy, 1, None, dummy, 8, dummy, dummy, (1 << 20) + 1, dummy,
                              None) == 1
     assert _hh().NOALLOC_MAX_MSGS == 1 << 20
+    # the feed: every argument error is found before any device call
+    h = vp()
+    assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 4, 100, None, None) == 1
+    assert L.hh_feed_open(None, 1, dummy, 8, 16, 4, 100, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 0, dummy, 8, 16, 4, 100, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 1, None, 8, 16, 4, 100, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 1, dummy, 8, 0, 4, 100, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 1, dummy, 8, 65537, 4, 100, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 1, 100, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 4097, 100, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 4, 0, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 4, 60001, None, ctypes.byref(h)) == 1
+    assert h.value is None
+    t = ctypes.c_uint64()
+    assert L.hh_feed_submit(None, 1, dummy, dummy, None, dummy, dummy, ctypes.byref(t)) == 1
+    assert L.hh_feed_poll(None) == 1
+    assert L.hh_feed_results(None) is None
+    assert L.hh_feed_close(None) == 1
 
 
 def test_no_device_reported_as_unsupported():
