@@ -213,51 +213,53 @@ hh_status hh_copy_segments(uint8_t* dst, uint64_t dst_bytes, const uint8_t* src,
 
 /* ---------------------------------------------------------------------------
  * Continuous hashing of long messages (serving): a persistent kernel takes
- * groups of messages from a queue in host memory while it runs and hashes
- * each message whole (Sec. 4.2-4.5, four threads per message), so that a
- * message submitted while others are being hashed starts at once on an idle
- * wave instead of waiting for the next launch.  Results reach host memory
- * directly.  One feed serves one caller thread at a time (calls on one feed
- * are serialised by a lock).
+ * messages from a queue in host memory while it runs and hashes each one
+ * whole (Sec. 4.2-4.5, four threads per message), so that a message submitted
+ * while others are being hashed starts without waiting for a launch.  Each
+ * hashing wave holds up to 16 messages at a time, taking a new one whenever
+ * one of its places is free (it looks every 2048 packets); results reach host
+ * memory directly.  One feed serves one caller thread at a time (calls on one
+ * feed are serialised by a lock).
  *
  * hh_feed_open: keys (device, n_keys x 4 words) and the byte buffer
  * data[0 .. data_bytes) (device) are fixed for the feed's life; the caller
- * keeps them alive and unmodified where submitted messages lie until their
+ * keeps them alive, and unmodified where submitted messages lie until their
  * results are seen.  `slots` result rows (1 .. HH_FEED_MAX_SLOTS) live in
- * pinned host memory owned by the feed.  `waves` (2 .. HH_FEED_MAX_WAVES)
- * one-wave workgroups are launched on `stream` (which then carries nothing
- * else while the feed is open): one dispatcher and waves - 1 hashing waves,
- * each hashing one group at a time.  Each launch ends by itself after
- * max_ms (1 .. HH_FEED_MAX_MS) milliseconds; hh_feed_submit and hh_feed_poll
- * launch again while submitted groups wait.  Allocates host and device
+ * pinned host memory owned by the feed, and at most `slots` messages are in
+ * flight.  `waves` (2 .. HH_FEED_MAX_WAVES) one-wave workgroups are launched
+ * on `stream` (which then carries nothing else while the feed is open): one
+ * dispatcher and waves - 1 hashing waves, which fill up in index order (an
+ * idle wave takes a message only while no lower one has a free place), so
+ * that few CUs carry the long chains beside other work.  Each launch stops
+ * taking messages after max_ms (1 .. HH_FEED_MAX_MS) milliseconds and ends
+ * once it has finished those it holds; hh_feed_submit and hh_feed_poll
+ * launch again while submitted messages wait.  Allocates host and device
  * memory (HH_ERR_OUT_OF_MEMORY). */
-#define HH_FEED_GROUP 16
 #define HH_FEED_MAX_SLOTS 65536u
-#define HH_FEED_MAX_WAVES 4096u
+#define HH_FEED_MAX_WAVES 65u
 #define HH_FEED_MAX_MS 60000u
 typedef struct hh_feed hh_feed;
 hh_status hh_feed_open(const uint64_t* keys, uint32_t n_keys, const uint8_t* data,
                        uint64_t data_bytes, uint32_t slots, uint32_t waves, uint32_t max_ms,
                        void* stream, hh_feed** feed);
 
-/* Queue one group of n (1 .. HH_FEED_GROUP) messages; the arrays are HOST
+/* Queue n (1 .. slots) messages, taken in this order; the arrays are HOST
  * arrays of n entries, read before the call returns.  Message i is
  * data[offsets[i] .. + lengths[i]) (clamped to data_bytes) under key
  * key_idx[i] (NULL: key 0; clamped to n_keys - 1), and its width_words[i]
- * (1, 2 or 4) hash words go to result row slot[i] (< slots).  The messages of
- * a group are hashed side by side and their results appear when the longest
- * is done, so a group should hold messages of similar length.  *first_ticket
+ * (1, 2 or 4) hash words go to result row slot[i] (< slots).  *first_ticket
  * receives the ticket of message 0; message i has ticket first + i (tickets
  * start at 1 and never repeat in a feed).  A slot must not be submitted
- * again until its result has been seen.  HH_ERR_BUSY: the queue holds
- * `slots` groups that no wave has taken yet; submit again later. */
+ * again until its result has been seen.  HH_ERR_BUSY (nothing queued): the
+ * queue has no room for n more messages until the kernel has read earlier
+ * ones; submit again later. */
 hh_status hh_feed_submit(hh_feed* feed, uint32_t n, const uint64_t* offsets,
                          const uint64_t* lengths, const uint32_t* key_idx,
                          const uint8_t* width_words, const uint32_t* slot,
                          uint64_t* first_ticket);
 
 /* Launch the kernel again if its last launch has ended while submitted
- * groups wait.  Call it from the loop that watches the results. */
+ * messages wait.  Call it from the loop that watches the results. */
 hh_status hh_feed_poll(hh_feed* feed);
 
 /* Result rows (host memory, 5 words per slot): row s holds the hash words of
@@ -266,7 +268,7 @@ hh_status hh_feed_poll(hh_feed* feed);
  * the words.  Valid until hh_feed_close; NULL for a null feed. */
 const volatile uint64_t* hh_feed_results(const hh_feed* feed);
 
-/* Stop the kernel (it finishes the groups it has taken), wait for it and
+/* Stop taking messages, wait for the kernel to finish those it holds and
  * free the feed. */
 hh_status hh_feed_close(hh_feed* feed);
 

@@ -1,31 +1,40 @@
 // hh_feed.hip -- continuous hashing of long messages for a serving loop.
 //
-// A persistent kernel takes groups of up to 16 messages from a queue in host
-// memory while it runs and hashes each message whole (Sec. 4.2-4.5, four
-// threads per message as in the quad kernel), writing each result and then
-// its ticket into host memory.  A message that is submitted while others are
-// being hashed starts within microseconds on an idle wave, instead of waiting
-// for the next launch of a chunked iteration.
+// A persistent kernel takes messages from a queue in host memory while it
+// runs and hashes each one whole (Sec. 4.2-4.5, four threads per message as
+// in the quad kernel), writing its result and then its ticket into host
+// memory.  Each hashing wave is a 16-place engine: its quads take messages
+// one by one as they become free, so messages that arrive at different times
+// share a wave (a wave's chain of Updates runs no slower with 16 messages
+// than with one, and every wave with a chain in it takes its SIMD's issue
+// slots), and a message starts within one round (kRoundPackets packets) of a
+// busy wave, or at once on an idle one.
 //
 // Shared memory (pinned host memory, fine-grained and mapped for the GPU):
-//   shared.tail       groups submitted so far (host writes)
+//   shared.tail       messages submitted so far (host writes)
 //   shared.exit       set by hh_feed_close (host writes)
-//   ring[cap]         group descriptors, group g in ring[g % cap] (host writes)
-//   consumed[cap]     g + 1 once a wave has read group g (GPU writes)
+//   ring[cap]         message descriptors, message i in ring[i % cap] (host writes)
+//   consumed[cap]     i + 1 once a wave has read message i (GPU writes)
 //   rows[slots][5]    four result words, then the ticket of the message whose
 //                     result they are (GPU writes)
 // Device memory:
-//   head              groups claimed so far (compare-and-swap by the waves)
+//   head              messages claimed so far (compare-and-swap by the waves)
 //   tail_seen         the dispatcher's latest copy of shared.tail
 //   exit_gen          launch generation that has been told to stop
+//   free_mask         bit w set while hashing wave w has a free place
+//
+// Packing: a wave that holds messages looks at the queue after every round;
+// a wave that holds none takes a message only when no hashing wave with a
+// lower index has a free place.  So new messages fill the busy waves and
+// then the lowest idle ones, and as few waves (and CUs) as possible carry
+// chains of Updates beside the other kernels on the GPU.
 //
 // Wave 0 of a launch is the dispatcher: it alone reads shared.tail and
 // shared.exit over the host link and republishes them in device memory, so
-// that idle waves poll the L2 and not the link.  Every launch ends by itself
-// after max_ms (plus a grace period for the waves): the host relaunches it
-// (hh_feed_submit, hh_feed_poll) while submitted groups wait.  A wave stops
-// only between groups, so a running launch never leaves a claimed group
-// unfinished.
+// that the other waves poll the L2 and not the link.  Every launch stops
+// taking messages after max_ms and ends when its waves have finished the
+// messages they hold: the host relaunches it (hh_feed_submit, hh_feed_poll)
+// while submitted messages wait.
 
 #include <atomic>
 #include <cstring>
@@ -38,21 +47,14 @@
 namespace hh {
 namespace {
 
-constexpr u32 kFeedGroup = 16;                 // messages per group: one wave, four threads each
-constexpr u64 kTicksPerMs = 100000;            // the real-time counter runs at 100 MHz
-constexpr u64 kGraceTicks = 50 * kTicksPerMs;  // waves outlive the dispatcher by at most this
+constexpr u64 kTicksPerMs = 100000;  // the real-time counter runs at 100 MHz
 constexpr u64 kNone = ~0ull;
-constexpr int kFeedRing = 48;                  // packets in flight per thread
+constexpr int kFeedRing = 48;            // packets in flight per thread
+constexpr u32 kRoundPackets = 2048;      // packets per message between two looks at the queue
 
 struct FeedReq {
     u64 offset, length, ticket;
     u32 key_idx, slot, width, pad;
-};
-
-struct FeedGroupDesc {
-    u64 n;
-    u64 pad[7];
-    FeedReq req[kFeedGroup];
 };
 
 struct FeedShared {
@@ -69,6 +71,8 @@ struct FeedDev {
     u64 pad1[15];
     u64 exit_gen;
     u64 pad2[15];
+    u64 free_mask;  // bit w: hashing wave w has a free place
+    u64 pad3[15];
 };
 
 struct FeedArgs {
@@ -78,7 +82,7 @@ struct FeedArgs {
     const u8* data;
     u64 data_bytes;
     const FeedShared* shared;
-    const FeedGroupDesc* ring;
+    const FeedReq* ring;
     u64* consumed;
     u64* rows;
     u64 slots;
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(64) void hh_feed_kernel(FeedArgs a) {
             while (true) {
                 const u64 t = sys_load(&a.shared->tail);
                 if (t != last) {
-                    // the groups below t were written before t: pass that on
+                    // the messages below t were written before t: pass that on
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
                     __hip_atomic_store(&a.dev->tail_seen, t, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -136,57 +140,119 @@ __global__ __launch_bounds__(64) void hh_feed_kernel(FeedArgs a) {
         }
         return;
     }
-    const u32 r = lane >> 2;
     const int q = (int)(lane & 3u);
+    const u32 leader = lane & ~3u;  // lane 4r leads quad r
+    const u32 w = blockIdx.x - 1u;   // hashing wave index (< 64)
+    const u64 my_bit = 1ull << w, lower = my_bit - 1ull;
+    bool bit_set = false;  // this wave's free_mask bit as last written
+    // the message this quad holds (every lane of a quad agrees on all but s)
+    bool active = false;
+    State1 s;
+    reset1(s, 0, q);
+    const u8* msg = a.data;
+    const u8* p = a.data;
+    u64 len = 0, rem = 0, ticket = 0;
+    u32 slot = 0, width = 0;
     while (true) {
-        // lane 0 claims the next group, or learns that the launch is over
-        u64 g = kNone;
-        if (lane == 0) {
-            while (true) {
-                const u64 t = dev_load(&a.dev->tail_seen);
-                u64 h = dev_load(&a.dev->head);
-                if (h < t) {
-                    if (__hip_atomic_compare_exchange_strong(&a.dev->head, &h, h + 1u,
+        // take messages for the free quads, unless the launch is over
+        const bool stop = dev_load(&a.dev->exit_gen) >= a.gen || ticks() - t0 > a.max_ticks;
+        const u64 free_q = __ballot(q == 0 && !active);
+        const bool busy = free_q != 0x1111111111111111ull;
+        // an idle wave leaves new messages to busy waves and lower idle ones
+        const bool may_take =
+            !stop && free_q && (busy || (dev_load(&a.dev->free_mask) & lower) == 0u);
+        u64 h = 0, m = 0;
+        if (may_take) {
+            if (lane == 0) {
+                const u64 want = (u64)__popcll(free_q);
+                while (true) {
+                    const u64 t = dev_load(&a.dev->tail_seen);
+                    u64 hh = dev_load(&a.dev->head);
+                    if (hh >= t) break;
+                    const u64 k = t - hh < want ? t - hh : want;
+                    if (__hip_atomic_compare_exchange_strong(&a.dev->head, &hh, hh + k,
                                                              __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT)) {
-                        g = h;
+                        h = hh;
+                        m = k;
                         break;
                     }
-                    continue;
                 }
-                if (dev_load(&a.dev->exit_gen) >= a.gen || ticks() - t0 > a.max_ticks + kGraceTicks)
-                    break;
-                __builtin_amdgcn_s_sleep(32);
             }
+            h = wave_broadcast(h);
+            m = wave_broadcast(m);
         }
-        // the claimed group's descriptor was written before the tail that
-        // announced it
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-        g = wave_broadcast(g);
-        if (g == kNone) return;
-        const FeedGroupDesc* d = a.ring + (g % a.cap);
-        const u64 n_raw = sys_load(&d->n);
-        const u32 n = n_raw < kFeedGroup ? (u32)n_raw : kFeedGroup;
-        const bool real = r < n;
-        const FeedReq* rq = &d->req[real ? r : 0u];
-        const u64 off = sys_load(&rq->offset), len = sys_load(&rq->length);
-        const u64 ticket = sys_load(&rq->ticket);
-        const u32 kidx = sys_load32(&rq->key_idx), slot = sys_load32(&rq->slot);
-        const u32 width = sys_load32(&rq->width);
-        // every lane holds its fields: the group's descriptor may be reused
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-        if (lane == 0) sys_store(&a.consumed[g % a.cap], g + 1u);
+        if (m) {
+            // the claimed descriptors were written before the tail that
+            // announced them
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            const u64 rank = (u64)__popcll(free_q & ((1ull << leader) - 1ull));
+            const bool take = !active && rank < m;
+            u64 idx = 0;
+            if (take) {
+                idx = h + rank;
+                const FeedReq* rq = a.ring + (idx % a.cap);
+                const u64 off = sys_load(&rq->offset), length = sys_load(&rq->length);
+                ticket = sys_load(&rq->ticket);
+                const u32 kidx = sys_load32(&rq->key_idx);
+                slot = sys_load32(&rq->slot);
+                width = sys_load32(&rq->width);
+                const Msg mm = message(a.data, a.data_bytes, off, length);
+                const u64 key_q =
+                    a.keys[4u * (u64)(kidx < a.n_keys ? kidx : a.n_keys - 1u) + (u32)q];
+                reset1(s, key_q, q);
+                msg = mm.p;
+                p = mm.p;
+                len = mm.len;
+                rem = mm.len >> 5;
+                active = true;
+            }
+            // every taker holds its descriptor's fields: the entries may be reused
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            if (take && q == 0) sys_store(&a.consumed[idx % a.cap], idx + 1u);
+        }
+        // publish whether this wave has a free place (after taking, and after
+        // the round below has finished messages)
+        const bool has_free = __ballot(q == 0 && !active) != 0u && !stop;
+        if (has_free != bit_set) {
+            if (lane == 0) {
+                if (has_free)
+                    __hip_atomic_fetch_or(&a.dev->free_mask, my_bit, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    __hip_atomic_fetch_and(&a.dev->free_mask, ~my_bit, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            bit_set = has_free;
+        }
+        if (!__ballot(active)) {
+            if (stop) return;
+            __builtin_amdgcn_s_sleep(32);
+            continue;
+        }
+        // one round: every quad with whole packets left absorbs up to
+        // kRoundPackets of them
+        if (active && rem) {
+            const u32 npk = (u32)(rem < kRoundPackets ? rem : kRoundPackets);
+            absorb_quad<kFeedRing>(s, p + 8u * (u32)q, npk);
+            p += 32u * (u64)npk;
+            rem -= npk;
+        }
+        // quads whose message has no whole packet left finish it
+        const bool fin = active && rem == 0u;
         u64 sum = 0;
-        if (real) {
-            const Msg m = message(a.data, a.data_bytes, off, len);
-            const u64 key_q = a.keys[4u * (u64)(kidx < a.n_keys ? kidx : a.n_keys - 1u) + (u32)q];
-            sum = hash_quad<kFeedRing>(key_q, m.p, m.len, q);
+        if (fin) {
+            const u32 r = (u32)(len & 31u);
+            const u64 tail = r ? remainder_lane(msg + 32u * (len >> 5), r, len, q) : 0;
+            if (r) remainder1(s, r, tail);
+            sum = finalize1(s);
         }
         const bool valid_w = width == 1u || width == 2u || width == 4u;
-        if (real && slot < a.slots && valid_w && (u32)q < width) sys_store(&a.rows[5u * slot + q], sum);
+        if (fin && slot < a.slots && valid_w && (u32)q < width) sys_store(&a.rows[5u * slot + q], sum);
         // the words are visible before the ticket that announces them
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-        if (real && slot < a.slots && q == 0) sys_store(&a.rows[5u * slot + 4u], ticket);
+        if (fin && slot < a.slots && q == 0) sys_store(&a.rows[5u * slot + 4u], ticket);
+        if (fin) active = false;
     }
 }
 
@@ -206,7 +272,7 @@ struct hh_feed {
     u64 max_ticks = 0;
     u8* host = nullptr;  // pinned, fine-grained: shared, ring, consumed, rows
     FeedShared* shared = nullptr;
-    FeedGroupDesc* ring = nullptr;
+    FeedReq* ring = nullptr;
     u64* consumed = nullptr;
     u64* rows = nullptr;
     u8* host_d = nullptr;  // the same memory as the GPU addresses it
@@ -222,12 +288,12 @@ namespace {
 u64 align64(u64 x) { return (x + 63u) & ~63ull; }
 
 // Relaunch the kernel when the last launch has ended (it stops by itself
-// after max_ms) and a submitted group is still unread.  Caller holds mu.
+// after max_ms) and a submitted message is still unread.  Caller holds mu.
 hh_status feed_keep_running(hh_feed* f) {
     if (f->tail == 0) return HH_OK;
     const u64 last = f->tail - 1u;
     const u64 seen = __atomic_load_n(&f->consumed[last % f->cap], __ATOMIC_ACQUIRE);
-    if (seen == last + 1u) return HH_OK;  // every group has been taken
+    if (seen == last + 1u) return HH_OK;  // every message has been taken
     if (f->launched) {
         const hipError_t q = hipEventQuery(f->done);
         if (q == hipErrorNotReady) return HH_OK;  // still running: it will take them
@@ -243,10 +309,10 @@ hh_status feed_keep_running(hh_feed* f) {
     a.data = f->data;
     a.data_bytes = f->data_bytes;
     const u64 ring_off = align64(sizeof(FeedShared));
-    const u64 cons_off = ring_off + align64((u64)f->cap * sizeof(FeedGroupDesc));
+    const u64 cons_off = ring_off + align64((u64)f->cap * sizeof(FeedReq));
     const u64 rows_off = cons_off + align64(8ull * f->cap);
     a.shared = (const FeedShared*)f->host_d;
-    a.ring = (const FeedGroupDesc*)(f->host_d + ring_off);
+    a.ring = (const FeedReq*)(f->host_d + ring_off);
     a.consumed = (u64*)(f->host_d + cons_off);
     a.rows = (u64*)(f->host_d + rows_off);
     a.slots = f->slots;
@@ -294,10 +360,10 @@ hh_status hh_feed_open(const uint64_t* keys, uint32_t n_keys, const uint8_t* dat
     f->data = data;
     f->data_bytes = data_bytes;
     f->slots = slots;
-    f->cap = slots;  // every group in flight holds at least one slot
+    f->cap = slots;  // every message in flight holds a slot
     f->waves = waves;
     f->max_ticks = (u64)max_ms * kTicksPerMs;
-    const u64 bytes = align64(sizeof(FeedShared)) + align64((u64)f->cap * sizeof(FeedGroupDesc)) +
+    const u64 bytes = align64(sizeof(FeedShared)) + align64((u64)f->cap * sizeof(FeedReq)) +
                       align64(8ull * f->cap) + 40ull * slots;
     void* host = nullptr;
     if (hipHostMalloc(&host, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
@@ -315,10 +381,10 @@ hh_status hh_feed_open(const uint64_t* keys, uint32_t n_keys, const uint8_t* dat
     }
     f->host_d = (u8*)host_d;
     const u64 ring_off = align64(sizeof(FeedShared));
-    const u64 cons_off = ring_off + align64((u64)f->cap * sizeof(FeedGroupDesc));
+    const u64 cons_off = ring_off + align64((u64)f->cap * sizeof(FeedReq));
     const u64 rows_off = cons_off + align64(8ull * f->cap);
     f->shared = (FeedShared*)f->host;
-    f->ring = (FeedGroupDesc*)(f->host + ring_off);
+    f->ring = (FeedReq*)(f->host + ring_off);
     f->consumed = (u64*)(f->host + cons_off);
     f->rows = (u64*)(f->host + rows_off);
     if (hipMalloc(&f->dev, sizeof(FeedDev)) != hipSuccess) {
@@ -327,8 +393,8 @@ hh_status hh_feed_open(const uint64_t* keys, uint32_t n_keys, const uint8_t* dat
         feed_free(f);
         return HH_ERR_OUT_OF_MEMORY;
     }
-    // synchronous: the counters are zero before any launch reads them
-    if (hipMemset(f->dev, 0, sizeof(FeedDev)) != hipSuccess ||
+    // ordered on the feed's stream before its first launch
+    if (hipMemsetAsync(f->dev, 0, sizeof(FeedDev), f->stream) != hipSuccess ||
         hipEventCreateWithFlags(&f->done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         feed_free(f);
@@ -341,32 +407,35 @@ hh_status hh_feed_open(const uint64_t* keys, uint32_t n_keys, const uint8_t* dat
 hh_status hh_feed_submit(hh_feed* f, uint32_t n, const uint64_t* offsets, const uint64_t* lengths,
                          const uint32_t* key_idx, const uint8_t* width_words,
                          const uint32_t* slot, uint64_t* first_ticket) {
-    if (!f || n == 0 || n > HH_FEED_GROUP || !offsets || !lengths || !width_words || !slot)
-        return HH_ERR_INVALID_ARG;
+    if (!f || n == 0 || !offsets || !lengths || !width_words || !slot) return HH_ERR_INVALID_ARG;
+    if (n > f->slots) return HH_ERR_INVALID_ARG;
     for (uint32_t i = 0; i < n; ++i) {
         const uint8_t w = width_words[i];
         if ((w != 1 && w != 2 && w != 4) || slot[i] >= f->slots) return HH_ERR_INVALID_ARG;
     }
     std::lock_guard<std::mutex> lock(f->mu);
-    const u64 e = f->tail % f->cap;
-    if (f->tail >= f->cap &&
-        __atomic_load_n(&f->consumed[e], __ATOMIC_ACQUIRE) != f->tail - f->cap + 1u)
-        return HH_ERR_BUSY;  // the group that used this entry has not been read yet
-    FeedGroupDesc& d = f->ring[e];
+    // every entry to be written must have been read by the wave that took
+    // the message submitted cap places earlier
     for (uint32_t i = 0; i < n; ++i) {
-        d.req[i].offset = offsets[i];
-        d.req[i].length = lengths[i];
-        d.req[i].ticket = f->next_ticket + i;
-        d.req[i].key_idx = key_idx ? key_idx[i] : 0u;
-        d.req[i].slot = slot[i];
-        d.req[i].width = width_words[i];
-        d.req[i].pad = 0;
+        const u64 idx = f->tail + i;
+        if (idx >= f->cap &&
+            __atomic_load_n(&f->consumed[idx % f->cap], __ATOMIC_ACQUIRE) != idx - f->cap + 1u)
+            return HH_ERR_BUSY;
     }
-    d.n = n;
+    for (uint32_t i = 0; i < n; ++i) {
+        FeedReq& d = f->ring[(f->tail + i) % f->cap];
+        d.offset = offsets[i];
+        d.length = lengths[i];
+        d.ticket = f->next_ticket + i;
+        d.key_idx = key_idx ? key_idx[i] : 0u;
+        d.slot = slot[i];
+        d.width = width_words[i];
+        d.pad = 0;
+    }
     if (first_ticket) *first_ticket = f->next_ticket;
     f->next_ticket += n;
-    ++f->tail;
-    // the descriptor is complete before the GPU can see the new tail
+    f->tail += n;
+    // the descriptors are complete before the GPU can see the new tail
     __atomic_store_n(&f->shared->tail, f->tail, __ATOMIC_RELEASE);
     return feed_keep_running(f);
 }

@@ -463,10 +463,6 @@ def release() -> None:
     _check(lib().hh_release())
 
 
-# messages per hh_feed_submit group (HH_FEED_GROUP in hh.h)
-FEED_GROUP = 16
-
-
 class Feed:
     """hh_feed_*: a persistent kernel that hashes long messages as they are
     submitted (see hh.h).  `keys` (n_keys x 4, device) and `data` (uint8,
@@ -491,9 +487,9 @@ class Feed:
             (ctypes.c_uint64 * (5 * self.slots)).from_address(base)).reshape(self.slots, 5)
 
     def submit(self, offsets, lengths, key_idx, widths, slots) -> int:
-        """Queue one group (at most FEED_GROUP messages; host arrays); returns
-        the first message's ticket (message i: ticket + i), or 0 when the
-        queue is full (submit again later)."""
+        """Queue messages (host arrays, taken in this order); returns the
+        first message's ticket (message i: ticket + i), or 0 when the queue
+        has no room for them yet (submit again later)."""
         o = np.ascontiguousarray(offsets, np.uint64)
         L = np.ascontiguousarray(lengths, np.uint64)
         k = np.ascontiguousarray(key_idx, np.uint32)
@@ -501,7 +497,7 @@ class Feed:
         s = np.ascontiguousarray(slots, np.uint32)
         n = o.size
         if not (L.size == k.size == w.size == s.size == n):
-            raise ValueError("group arrays must have equal lengths")
+            raise ValueError("message arrays must have equal lengths")
         t = _u64()
         st = lib().hh_feed_submit(self._h, n, o.ctypes.data, L.ctypes.data, k.ctypes.data,
                                   w.ctypes.data, s.ctypes.data, ctypes.byref(t))

@@ -159,13 +159,16 @@ class GpuBackend:
     requests' lane) on a stream of its own with its own staging ring and
     output buffer, so that a long lane iteration never holds up the short
     requests' iterations.  Admission runs on the compute stream; the lane 1
-    stream only ever receives that lane's iterations."""
+    stream only ever receives that lane's iterations, or the feed's
+    persistent kernel (feed_submit), which hashes a long request whole and
+    writes its result into host memory."""
 
     RING = 6   # staging sets per lane; more than the scheduler's run-ahead + 1
     LANES = 2
+    FEED = True
 
     def __init__(self, keys: np.ndarray, payload: np.ndarray, arena_bytes: int, max_slots: int,
-                 source: str = "device"):
+                 source: str = "device", feed_waves: int = 64, feed_max_ms: int = 1000):
         import torch
         from . import hh
         self.torch, self.hh = torch, hh
@@ -229,6 +232,13 @@ class GpuBackend:
         if source == "host":
             self._warm_stream(self.copy_stream)
         self.launcher.submit(self._warm_stream, self.lane_streams[1]).result()
+        # the long requests' feed: a persistent kernel on the lane 1 stream
+        # that hashes each long request whole from the arena; it launches on
+        # the first submitted group, so a chunked long lane keeps that
+        # stream to itself
+        self.slot_key = np.zeros(max_slots, np.uint32)
+        self._feed = hh.Feed(self.keys, self.arena, max_slots, feed_waves, feed_max_ms,
+                             self.lane_streams[1])
 
     def _warm_stream(self, stream) -> None:
         with self.torch.cuda.stream(stream):
@@ -267,6 +277,7 @@ class GpuBackend:
         h[16 * n:24 * n].view(np.int64)[:] = lens
         h[24 * n:28 * n].view(np.int32)[:] = batch.key_idx
         h[28 * n:32 * n].view(np.int32)[:] = batch.slot
+        self.slot_key[batch.slot] = batch.key_idx
         d = self.d_adm[lane][i]
         d[:32 * n].copy_(self.h_adm[lane][i][:32 * n], non_blocking=True)
         if self.source == "device":
@@ -390,7 +401,23 @@ class GpuBackend:
         ev, res = self._resolve(ticket)
         return None if res is None else res.numpy().view(np.uint64)
 
+    def feed_submit(self, slots, arena_offs, lengths, widths) -> int:
+        """Hand one group of admitted requests (at most FEED_GROUP) to the
+        feed; returns the first request's ticket, or 0 if the queue is full.
+        A request's result appears in feed_rows()[slot] with its ticket."""
+        return self._feed.submit(arena_offs, lengths, self.slot_key[slots], widths, slots)
+
+    def feed_rows(self) -> np.ndarray:
+        """(max_slots, 5) uint64: hash words, then the ticket they belong to."""
+        return self._feed.rows
+
+    def feed_poll(self) -> None:
+        self._feed.poll()
+
     def close(self) -> None:
+        if self._feed is not None:
+            self._feed.close()
+            self._feed = None
         self.launcher.shutdown(wait=True)
 
 
@@ -401,12 +428,20 @@ class Server:
     the long lane, long_chunk_bytes per iteration, on their own stream; the
     others advance chunk_bytes per iteration in lane 0.  Every lane keeps its
     own iterations in flight, so the long requests' few large steps never
-    stretch the short requests' iterations."""
+    stretch the short requests' iterations.
+
+    long_mode="feed" (with a backend that has a feed): instead of chunked
+    iterations, each long request goes whole to the backend's persistent
+    kernel as soon as its admission is done (longest first), and is retired
+    when its result row shows its ticket: it neither waits for an iteration
+    to join nor for the longest chunk of one.  long_mode="chunks" keeps the
+    chunked long lane."""
 
     def __init__(self, backend, budget_bytes: int, chunk_bytes: int = 1 << 16,
                  max_active: Optional[int] = None, clock=time.perf_counter,
                  sleep=time.sleep, run_ahead: int = 2, long_chunk_bytes: int = 1 << 20,
-                 long_min_bytes: Optional[int] = None, poll_s: float = 5e-4):
+                 long_min_bytes: Optional[int] = None, poll_s: float = 5e-4,
+                 long_mode: Optional[str] = None, feed_poll_s: float = 5e-5):
         for c in (chunk_bytes, long_chunk_bytes):
             if c <= 0 or c % 32:
                 raise ValueError("chunk sizes must be positive multiples of 32")
@@ -417,9 +452,20 @@ class Server:
         self.chunk = chunk_bytes
         self.lanes = min(2, getattr(backend, "LANES", 1))
         self.chunks = [chunk_bytes, long_chunk_bytes]
-        self.long_min = 16 * chunk_bytes if long_min_bytes is None else long_min_bytes
         self.lane_run_ahead = [run_ahead, 1]
         self.poll_s = poll_s
+        has_feed = getattr(backend, "FEED", False) and self.lanes > 1
+        if long_mode is None:
+            long_mode = "feed" if has_feed else "chunks"
+        if long_mode not in ("feed", "chunks") or (long_mode == "feed" and not has_feed):
+            raise ValueError("long_mode must be 'chunks', or 'feed' with a feed backend")
+        self.long_mode = long_mode
+        # requests longer than this take the long lane: in the feed, from
+        # four chunks up (they are hashed whole there); chunked, from 16
+        if long_min_bytes is None:
+            long_min_bytes = (4 if long_mode == "feed" else 16) * chunk_bytes
+        self.long_min = long_min_bytes
+        self.feed_poll_s = feed_poll_s
         self.arena = Arena(budget_bytes)
         self.max_active = max_active or backend.max_slots
         self.free_slots = list(range(backend.max_slots))[::-1]
@@ -487,6 +533,11 @@ class Server:
         gated: collections.deque = collections.deque()  # (admission ticket, slots)
         # per lane: (ticket, finishing slots) in launch order
         inflight = [collections.deque() for _ in range(self.lanes)]
+        feed = self.long_mode == "feed"
+        fed = np.zeros(S, bool)             # handed to the feed, result not yet seen
+        fticket = np.zeros(S, np.uint64)    # the feed ticket of that request
+        n_fed = 0
+        self.feed_submits = 0
         t0 = self.clock()
         arrived = 0   # requests [0, arrived) have arrived
         head = 0      # requests [head, arrived) are queued
@@ -500,9 +551,11 @@ class Server:
             if block:
                 self.backend.wait(ticket)
             words = self.backend.results(ticket)
+            if len(fin):
+                retire(fin, words)
+
+        def retire(fin: np.ndarray, words: np.ndarray) -> None:
             t = self.clock() - t0
-            if not len(fin):
-                return
             ridx = owner[fin]
             results[ridx] = words[:len(fin), :4]
             t_done[ridx] = t
@@ -572,10 +625,35 @@ class Server:
             # long-lane requests whose admission has completed may advance
             while gated and self.backend.done(gated[0][0]):
                 ready[gated.popleft()[1]] = True
+            # feed mode: long requests whose admission is done go whole to the
+            # feed, longest first
+            if feed:
+                g = np.flatnonzero(busy & (lane == 1) & ready)
+                if g.size:
+                    g = g[np.argsort(-length[g], kind="stable")]
+                    tk = self.backend.feed_submit(g, base[g], length[g], width[g])
+                    if tk:  # else the queue is full: they wait for the next pass
+                        fticket[g] = tk + np.arange(g.size, dtype=np.uint64)
+                        fed[g] = True
+                        busy[g] = False
+                        n_busy -= g.size
+                        n_fed += g.size
+                        self.feed_submits += 1
+                if n_fed:
+                    sub = np.flatnonzero(fed)
+                    rows = self.backend.feed_rows()
+                    fin = sub[rows[sub, 4] == fticket[sub]]
+                    if fin.size:
+                        fed[fin] = False
+                        n_fed -= fin.size
+                        retire(fin, rows[fin, :4].copy())
+                    self.backend.feed_poll()
             # per lane, one chunk for every busy request of the lane (whole
             # packets, or its final rest), unless the lane is far enough ahead
             launched = False
             for ln in range(self.lanes):
+                if feed and ln == 1:
+                    continue
                 if len(inflight[ln]) > self.lane_run_ahead[ln]:
                     continue
                 idx = (np.flatnonzero(busy & (lane == ln) & ready) if self.lanes > 1
@@ -606,14 +684,16 @@ class Server:
             if not launched:
                 if inflight[0]:
                     harvest(0, True)  # short iterations: wait for the oldest
-                elif (any(inflight) or gated) and head == arrived:
-                    # only long iterations or admissions in flight: sleep
-                    # until the next arrival (at most poll_s)
+                elif (any(inflight) or gated or n_fed) and head == arrived:
+                    # only long work or admissions in flight: sleep until the
+                    # next arrival (at most poll_s, or feed_poll_s while the
+                    # feed holds requests)
                     nxt = (arrival[arrived] - (self.clock() - t0) if arrived < n_total
                            else self.poll_s)
-                    self.sleep(max(0.0, min(self.poll_s, nxt)))
-            if (not n_busy and not any(inflight) and not gated and head == arrived
-                    and arrived < n_total):
+                    cap = self.feed_poll_s if n_fed else self.poll_s
+                    self.sleep(max(0.0, min(cap, nxt)))
+            if (not n_busy and not any(inflight) and not gated and not n_fed
+                    and head == arrived and arrived < n_total):
                 self.sleep(max(0.0, min(1e-3, arrival[arrived] - (self.clock() - t0))))
         t_end = self.clock() - t0
         # fill in the Request objects
@@ -651,6 +731,7 @@ class Server:
             "one_chunk_p99_ms": float(np.percentile(lat_one, 99) * 1e3),
             "chunk_bytes": self.chunk, "budget_bytes": self.budget,
             "max_bytes_in_flight": self.max_bytes_in_flight,
+            "long_mode": self.long_mode, "long_min_bytes": self.long_min,
         }
 
 
@@ -662,14 +743,16 @@ def requests_from_trace(trace) -> List[Request]:
 
 def serve_trace(trace, budget_bytes: int = 32 << 30, chunk_bytes: int = 1 << 16,
                 max_slots: int = 16384, source: str = "device", time_scale: float = 1.0,
-                **server_kw):
+                feed_waves: int = 64, **server_kw):
     """Run one trace on the GPU; returns (metrics, requests).  server_kw go to
-    Server (long_chunk_bytes, long_min_bytes, poll_s, run_ahead)."""
+    Server (long_mode, long_chunk_bytes, long_min_bytes, poll_s, run_ahead);
+    feed_waves sizes the backend's feed (one dispatcher wave, the others
+    hashing up to 16 requests each)."""
     reqs = requests_from_trace(trace)
     for r in reqs:
         r.arrival *= time_scale
     arena = min(budget_bytes, max(GRANULE, sum(Server.reservation(r.length) for r in reqs)))
-    backend = GpuBackend(trace.keys, trace.data, arena, max_slots, source)
+    backend = GpuBackend(trace.keys, trace.data, arena, max_slots, source, feed_waves)
     server = Server(backend, budget_bytes=arena if arena < budget_bytes else budget_bytes,
                     chunk_bytes=chunk_bytes, **server_kw)
     try:
@@ -678,6 +761,8 @@ def serve_trace(trace, budget_bytes: int = 32 << 30, chunk_bytes: int = 1 << 16,
         backend.close()
     m["budget_bytes"] = budget_bytes
     m["source"] = source
+    if server.long_mode == "feed":
+        m["feed_waves"] = feed_waves
     return m, reqs
 
 
@@ -741,8 +826,14 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--source", default="device", choices=["device", "host"])
     ap.add_argument("--long-chunk", type=int, default=1 << 20)
+    ap.add_argument("--long-mode", default=None, choices=["feed", "chunks"],
+                    help="long requests whole in the feed's persistent kernel (default) or "
+                         "in chunked iterations")
     ap.add_argument("--long-min", type=int, default=None,
-                    help="requests longer than this take the long lane (default 16 chunks)")
+                    help="requests longer than this take the long lane (default 4 chunks "
+                         "with the feed, 16 chunked)")
+    ap.add_argument("--feed-waves", type=int, default=64,
+                    help="feed workgroups: one dispatcher, the others 16 requests each")
     ap.add_argument("--poll-us", type=float, default=500.0)
     ap.add_argument("--max-slots", type=int, default=16384,
                     help="request states held on the device (128 B each)")
@@ -751,7 +842,8 @@ def main(argv=None):
         ap.error("--max-slots must be at least 1")
     loads = tuple(float(x) for x in args.loads.split(",") if x)
     kw = dict(long_chunk_bytes=args.long_chunk, long_min_bytes=args.long_min,
-              poll_s=args.poll_us * 1e-6, max_slots=args.max_slots)
+              poll_s=args.poll_us * 1e-6, max_slots=args.max_slots, long_mode=args.long_mode,
+              feed_waves=args.feed_waves)
     for p in load_sweep(args.requests, loads, args.chunk, int(args.budget_gib * 2**30), args.source,
                         **kw):
         p.update({k: v for k, v in kw.items()})

@@ -88,3 +88,38 @@ class CpuBackend:
 
     def results(self, ticket):
         return ticket
+
+
+class FeedCpuBackend(CpuBackend):
+    """CpuBackend with a feed: submitted requests are hashed whole at once
+    (the longest one's cost advances the clock) and their rows show the
+    results and tickets."""
+    FEED = True
+
+    def __init__(self, *args, **kw):
+        super().__init__(*args, **kw)
+        self.rows = np.zeros((self.max_slots, 5), np.uint64)
+        self.next_ticket = 1
+        self.submits = []   # (slots, lengths) per submit call
+
+    def feed_submit(self, slots, arena_offs, lengths, widths):
+        assert len(slots) >= 1
+        t = self.next_ticket
+        self.next_ticket += len(slots)
+        self.submits.append((np.asarray(slots).copy(), np.asarray(lengths).copy()))
+        for i, (slot, off, n) in enumerate(zip(np.asarray(slots).tolist(),
+                                               np.asarray(arena_offs).tolist(),
+                                               np.asarray(lengths).tolist())):
+            c = self.cats.pop(slot)
+            c.append(self.arena[off:off + n])
+            self.rows[slot, :4] = c.finish(4)
+            self.rows[slot, 4] = t + i
+            del self.live[slot]
+        self.clock.t += self.launch_s + max(np.asarray(lengths).tolist()) * self.ns_per_byte * 1e-9
+        return t
+
+    def feed_rows(self):
+        return self.rows
+
+    def feed_poll(self):
+        pass

@@ -90,7 +90,7 @@ def test_invalid_arguments_rejected_without_device():
     assert L.hh_feed_open(dummy, 1, dummy, 8, 0, 4, 100, None, ctypes.byref(h)) == 1
     assert L.hh_feed_open(dummy, 1, dummy, 8, 65537, 4, 100, None, ctypes.byref(h)) == 1
     assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 1, 100, None, ctypes.byref(h)) == 1
-    assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 4097, 100, None, ctypes.byref(h)) == 1
+    assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 66, 100, None, ctypes.byref(h)) == 1
     assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 4, 0, None, ctypes.byref(h)) == 1
     assert L.hh_feed_open(dummy, 1, dummy, 8, 16, 4, 60001, None, ctypes.byref(h)) == 1
     assert h.value is None

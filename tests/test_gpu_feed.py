@@ -1,7 +1,8 @@
 """The feed (hh_feed_*): a persistent kernel that hashes long messages as they
 are submitted.  Every result equals the oracle's; a message submitted while a
-much longer one is being hashed finishes first; slots are reused; a launch
-that has ended by its time limit is relaunched while groups wait."""
+much longer one is being hashed finishes first; a wave's 16 places are reused
+as messages finish; slots are reused; a launch that has ended by its time
+limit is relaunched while messages wait."""
 import time
 
 import numpy as np
@@ -40,7 +41,8 @@ def _wait(feed, slots, tickets, limit_s=20.0):
 
 
 def _submit_groups(feed, groups, offsets, lengths, key_idx, widths):
-    """groups: list of index arrays; slot = message index.  Returns tickets."""
+    """groups: index arrays submitted one call each; slot = message index.
+    Returns the tickets."""
     tickets = np.zeros(lengths.size, np.uint64)
     for g in groups:
         while True:
@@ -59,7 +61,7 @@ def _check(rows, want, widths):
         assert [int(x) for x in rows[j, :w]] == [int(x) for x in want[j, :w]], j
 
 
-def test_groups_of_every_size_match_the_oracle(hh):
+def test_messages_of_every_length_match_the_oracle(hh):
     rng = np.random.default_rng(71)
     lens = np.concatenate([np.arange(0, 70), rng.integers(70, 5000, 60),
                            rng.integers(5000, 400000, 30), [1 << 20, (1 << 20) + 31]])
@@ -71,7 +73,7 @@ def test_groups_of_every_size_match_the_oracle(hh):
     perm = rng.permutation(n)
     groups, i = [], 0
     while i < n:
-        k = int(rng.integers(1, 17))
+        k = int(rng.integers(1, 40))
         groups.append(perm[i:i + k])
         i += k
     k_t, d_t = dev(keys, torch.int64), dev(data)
@@ -79,7 +81,7 @@ def test_groups_of_every_size_match_the_oracle(hh):
     feed = hh.Feed(k_t, d_t, slots=n, waves=8, max_ms=2000,
                    stream=torch.cuda.Stream())
     try:
-        announce("feed groups", n, len(groups))
+        announce("feed messages", n, len(groups))
         tickets = _submit_groups(feed, groups, offsets, lengths, key_idx, widths)
         rows = _wait(feed, np.arange(n), tickets)
     finally:
@@ -145,7 +147,29 @@ def test_slots_reused_and_launches_renewed(hh):
         feed.close()
 
 
-def test_bad_group_arguments_rejected(hh):
+def test_one_wave_reuses_its_places(hh):
+    # one hashing wave (16 places) takes 60 messages of mixed lengths one by
+    # one as its places free up
+    rng = np.random.default_rng(75)
+    data, offsets, lengths = _buffer(rng, rng.integers(0, 300000, 60))
+    n = lengths.size
+    keys = rng.integers(0, 2**64, size=(2, 4), dtype=np.uint64)
+    key_idx = rng.integers(0, 2, n).astype(np.uint32)
+    widths = np.array([1, 2, 4], np.uint8)[rng.integers(0, 3, n)]
+    k_t, d_t = dev(keys, torch.int64), dev(data)
+    torch.cuda.synchronize()
+    feed = hh.Feed(k_t, d_t, slots=n, waves=2, max_ms=2000, stream=torch.cuda.Stream())
+    try:
+        announce("feed one wave", n)
+        tickets = _submit_groups(feed, [np.arange(n)], offsets, lengths, key_idx, widths)
+        rows = _wait(feed, np.arange(n), tickets)
+    finally:
+        feed.close()
+    want = oracle_ref(4, keys, key_idx, data, offsets, lengths)
+    _check(rows, want, widths)
+
+
+def test_bad_arguments_rejected(hh):
     rng = np.random.default_rng(74)
     data, offsets, lengths = _buffer(rng, [100, 200])
     keys = rng.integers(0, 2**64, size=(1, 4), dtype=np.uint64)
@@ -159,9 +183,9 @@ def test_bad_group_arguments_rejected(hh):
             feed.submit(offsets[:1], lengths[:1], z, np.array([3], np.uint8), np.array([0]))
         with pytest.raises(hh.HHError):
             feed.submit(offsets[:1], lengths[:1], z, np.ones(1, np.uint8), np.array([2]))
-        with pytest.raises(hh.HHError):
-            feed.submit(np.zeros(17, np.uint64), np.zeros(17, np.uint64),
-                        np.zeros(17, np.uint32), np.ones(17, np.uint8), np.zeros(17))
+        with pytest.raises(hh.HHError):   # more messages than slots
+            feed.submit(np.zeros(3, np.uint64), np.zeros(3, np.uint64),
+                        np.zeros(3, np.uint32), np.ones(3, np.uint8), np.zeros(3))
         assert feed.rows[:, 4].tolist() == [0, 0]   # nothing was queued
     finally:
         feed.close()

@@ -17,20 +17,25 @@ def hh():
     return require_gpu()
 
 
-@pytest.mark.parametrize("source,long_chunk", [("device", 1 << 20), ("host", 1 << 20),
-                                               ("device", 8192)])
-def test_serving_results_match_alone_and_oracle(hh, source, long_chunk):
-    # requests over 64 KiB take the long lane (its own stream); with 8 KiB
-    # long chunks they run several long-lane iterations beside the short ones
-    announce("serving", source, long_chunk)
+@pytest.mark.parametrize("source,long_chunk,long_mode", [
+    ("device", 1 << 20, "feed"), ("host", 1 << 20, "feed"), ("device", 1 << 20, "chunks"),
+    ("host", 1 << 20, "chunks"), ("device", 8192, "chunks")])
+def test_serving_results_match_alone_and_oracle(hh, source, long_chunk, long_mode):
+    # requests over 64 KiB take the long lane (its own stream): whole, in the
+    # feed's persistent kernel, or in chunked iterations (with 8 KiB chunks,
+    # several long-lane iterations beside the short ones)
+    announce("serving", source, long_chunk, long_mode)
     tr = workloads.serving_trace(400, 20000.0, lo=1, hi=200000, n_keys=16, seed=99)
     tr.lengths[::23] = 0
     budget = 8 << 20
     backend = serve.GpuBackend(tr.keys, tr.data, budget, 256, source)
     srv = serve.Server(backend, budget_bytes=budget, chunk_bytes=4096,
-                       long_chunk_bytes=long_chunk)
+                       long_chunk_bytes=long_chunk, long_mode=long_mode)
     reqs = serve.requests_from_trace(tr)
-    m = srv.run(reqs)
+    try:
+        m = srv.run(reqs)
+    finally:
+        backend.close()
     assert m["completed"] == len(reqs)
     assert m["max_bytes_in_flight"] <= budget
     # alone: each request through the one-shot batched kernel, one message per call
@@ -200,15 +205,16 @@ def test_widths_other_than_1_2_4_write_nothing(hh):
         assert torch.equal(states[fin], before[fin]), fn
 
 
-@pytest.mark.parametrize("arrivals", ["saturation", "poisson"])
-def test_serving_at_benchmark_settings(hh, arrivals):
+@pytest.mark.parametrize("arrivals,long_mode", [("saturation", "feed"), ("poisson", "feed"),
+                                               ("saturation", "chunks"), ("poisson", "chunks")])
+def test_serving_at_benchmark_settings(hh, arrivals, long_mode):
     # the settings the benchmark's serving runs use: 64 KiB chunks, 1 MiB
     # long-lane chunks, power-law lengths on [8 B, 16 MiB], 64 keys, widths
     # 1/2/4, device ingress; a few requests of 4-16 MiB span many long-lane
     # iterations beside the short ones.  Every result equals the oracle and
     # the request hashed on its own by the one-shot batched path.
     from paper_1612_06257_amd import workloads as W
-    announce("serving at bench settings", arrivals)
+    announce("serving at bench settings", arrivals, long_mode)
     tr = W.serving_trace(500, 40000.0, seed=W.SEED_BASE + 77, materialize=False)
     lens = tr.lengths.copy()
     lens[[3, 97, 211, 402]] = [1 << 24, (1 << 24) - 1, (5 << 20) + 17, (4 << 20) + 32]
@@ -219,7 +225,8 @@ def test_serving_at_benchmark_settings(hh, arrivals):
     tr.data = rng.integers(0, 256, int(lens.sum()), dtype=np.uint8)
     if arrivals == "saturation":
         tr.arrival_s[:] = 0.0
-    m, reqs = serve.serve_trace(tr, chunk_bytes=1 << 16, long_chunk_bytes=1 << 20)
+    m, reqs = serve.serve_trace(tr, chunk_bytes=1 << 16, long_chunk_bytes=1 << 20,
+                                long_mode=long_mode)
     assert m["completed"] == len(reqs) == tr.n
     got = {r.rid: r.result for r in reqs}
     keys = torch.from_numpy(tr.keys).view(torch.int64).cuda()

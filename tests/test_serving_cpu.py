@@ -164,3 +164,44 @@ def test_collector_off_during_the_loop_and_restored():
             assert gc.isenabled() == enabled
         finally:
             gc.enable()
+
+
+def test_feed_mode_results_equal_one_shot():
+    # long requests go whole to the feed, longest first, each exactly once;
+    # every result is exact
+    from _serve_cpu import FeedCpuBackend
+    tr = _trace(300, 3000.0, hi=9000, seed=51)
+    clock = VirtualClock()
+    reqs = serve.requests_from_trace(tr)
+    be = FeedCpuBackend(tr.keys, tr.data, 1 << 18, 128, clock)
+    srv = serve.Server(be, budget_bytes=1 << 18, chunk_bytes=64, long_min_bytes=2048,
+                       clock=clock, sleep=clock.sleep)
+    assert srv.long_mode == "feed"
+    m = srv.run(reqs)
+    assert m["completed"] == len(reqs)
+    assert be.submits and be.lane_launches[1] == 0
+    n_long = sum(r.length > 2048 for r in reqs)
+    assert sum(len(g) for g, _ in be.submits) == n_long
+    for g, lens in be.submits:
+        assert np.all(np.diff(lens.astype(np.int64)) <= 0)   # longest first
+    for r in reqs:
+        msg = tr.data[r.src:r.src + r.length]
+        assert r.result == tuple(oracle.hash_words(tr.keys[r.key_idx], msg, r.width)), r.rid
+
+
+def test_chunked_long_lane_still_selectable():
+    from _serve_cpu import FeedCpuBackend
+    tr = _trace(80, 3000.0, hi=9000, seed=53)
+    clock = VirtualClock()
+    reqs = serve.requests_from_trace(tr)
+    be = FeedCpuBackend(tr.keys, tr.data, 1 << 17, 64, clock)
+    srv = serve.Server(be, budget_bytes=1 << 17, chunk_bytes=64, long_chunk_bytes=256,
+                       long_min_bytes=2048, clock=clock, sleep=clock.sleep, long_mode="chunks")
+    assert srv.run(reqs)["completed"] == len(reqs)
+    assert not be.submits and be.lane_launches[1] > 0
+    for r in reqs:
+        msg = tr.data[r.src:r.src + r.length]
+        assert r.result == tuple(oracle.hash_words(tr.keys[r.key_idx], msg, r.width)), r.rid
+    with pytest.raises(ValueError):
+        serve.Server(CpuBackend(tr.keys, tr.data, 1 << 17, 64, clock), budget_bytes=1 << 17,
+                     long_mode="feed")
