@@ -778,11 +778,13 @@ def results_array(reqs: List[Request], n: int) -> np.ndarray:
 
 def load_sweep(n_requests: int = 10000, loads=(0.25, 0.5, 0.8), chunk_bytes: int = 1 << 16,
                budget_bytes: int = 32 << 30, source: str = "device", seed: Optional[int] = None,
-               with_results: bool = False, **server_kw):
+               with_results: bool = False, rates=None, **server_kw):
     """Saturation run (every request arrives at t=0), then Poisson loads at
-    the given fractions of the measured saturation request rate.  Every point
-    serves the same requests (lengths, payloads, keys, widths).  With
-    with_results, returns (points, trace, per-point results_array)."""
+    the given fractions of the measured saturation request rate (or, with
+    `rates`, at those offered requests/s, so that runs of different settings
+    see the same arrivals).  Every point serves the same requests (lengths,
+    payloads, keys, widths).  With with_results, returns (points, trace,
+    per-point results_array)."""
     from . import workloads as W
     kw = {} if seed is None else {"seed": seed}
     base = W.serving_trace(n_requests, 1.0, **kw)
@@ -791,12 +793,14 @@ def load_sweep(n_requests: int = 10000, loads=(0.25, 0.5, 0.8), chunk_bytes: int
     sat_rate = sat["requests_per_s"]
     out = [dict(sat, load="saturation", offered_requests_per_s=None)]
     results = [results_array(reqs, base.n)] if with_results else None
-    for f in loads:
-        tr = W.serving_trace(n_requests, f * sat_rate, materialize=False, **kw)
+    points = ([(f, f * sat_rate) for f in loads] if rates is None
+              else [(r / sat_rate, float(r)) for r in rates])
+    for f, rate in points:
+        tr = W.serving_trace(n_requests, rate, materialize=False, **kw)
         tr.data, tr.offsets, tr.lengths = base.data, base.offsets, base.lengths
         tr.key_idx, tr.width_words, tr.keys = base.key_idx, base.width_words, base.keys
         m, reqs = serve_trace(tr, budget_bytes, chunk_bytes, source=source, **server_kw)
-        out.append(dict(m, load=f, offered_requests_per_s=f * sat_rate))
+        out.append(dict(m, load=f, offered_requests_per_s=rate))
         if with_results:
             results.append(results_array(reqs, base.n))
     return (out, base, results) if with_results else out
@@ -822,6 +826,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--loads", default="0.25,0.5,0.8")
+    ap.add_argument("--rates", default=None,
+                    help="offered requests/s per point (comma list), instead of --loads")
     ap.add_argument("--chunk", type=int, default=1 << 16)
     ap.add_argument("--budget-gib", type=float, default=32.0)
     ap.add_argument("--source", default="device", choices=["device", "host"])
@@ -844,9 +850,10 @@ def main(argv=None):
     kw = dict(long_chunk_bytes=args.long_chunk, long_min_bytes=args.long_min,
               poll_s=args.poll_us * 1e-6, max_slots=args.max_slots, long_mode=args.long_mode,
               feed_waves=args.feed_waves)
+    rates = [float(x) for x in args.rates.split(",") if x] if args.rates else None
     for p in load_sweep(args.requests, loads, args.chunk, int(args.budget_gib * 2**30), args.source,
-                        **kw):
-        p.update({k: v for k, v in kw.items()})
+                        rates=rates, **kw):
+        p.update({k: v for k, v in kw.items() if v is not None})
         print(json.dumps(p), flush=True)
 
 
