@@ -1,15 +1,17 @@
 """Serving loop: continuous batching of hash requests on one GPU.
 
 A request is (key index, payload bytes, output width 1/2/4 words).  The loop
-keeps every admitted request's 1024-bit state and payload on the device and
-advances all of them together: each scheduler iteration gives every active
-request of a lane one chunk (a multiple of 32 bytes, or its whole
+keeps every admitted request's payload on the device.  Requests up to four
+chunks (256 KiB) advance together in lane 0: each scheduler iteration gives
+every active request one 64 KiB chunk (a multiple of 32 bytes, or its whole
 remainder), launched as one kernel that mixes the updates and the
-finalizations of the lane's requests.  Requests up to 1 MiB use 64 KiB
-chunks in lane 0; longer ones use 1 MiB chunks in the long lane, on a stream
-of their own.  Only size mod 32 enters HighwayHash (Sec. 4.5 of the paper),
-so a long request resumes from its state each iteration and no length
-counter is kept.
+finalizations, with each request's 1024-bit state kept on the device between
+iterations (only size mod 32 enters HighwayHash, Sec. 4.5 of the paper, so a
+request resumes from its state and no length counter is kept).  Longer
+requests go whole to the feed: a persistent kernel on a stream of its own
+that takes them as they arrive and writes each hash into pinned host memory
+(or, with long_mode="chunks", they advance 1 MiB per iteration in a second
+lane of chunked iterations).
 
 Requests that arrive while others are on the GPU are admitted as soon as a
 state slot and device memory (the admission budget: payload bytes rounded to
@@ -20,6 +22,7 @@ launches overlap the device work; the scheduler keeps its request state in
 arrays and admits and retires requests in bulk.
 
     python -m paper_1612_06257_amd.serve [--requests N] [--loads 0.25,0.5,0.8]
+        [--rates R1,R2,...] [--long-mode feed|chunks]
 
 prints one JSON line per load point: offered rate, GB/s, requests/s,
 p50/p90/p99 latency.
@@ -422,20 +425,19 @@ class GpuBackend:
 
 
 class Server:
-    """Scheduler: admission under the budget, chunked continuous batching.
+    """Scheduler: admission under the budget, continuous batching.
 
-    With a two-lane backend, requests longer than long_min_bytes advance in
-    the long lane, long_chunk_bytes per iteration, on their own stream; the
-    others advance chunk_bytes per iteration in lane 0.  Every lane keeps its
-    own iterations in flight, so the long requests' few large steps never
-    stretch the short requests' iterations.
+    Requests up to long_min_bytes advance chunk_bytes per iteration in lane
+    0.  With a two-lane backend, longer requests take the long lane:
 
-    long_mode="feed" (with a backend that has a feed): instead of chunked
-    iterations, each long request goes whole to the backend's persistent
-    kernel as soon as its admission is done (longest first), and is retired
-    when its result row shows its ticket: it neither waits for an iteration
-    to join nor for the longest chunk of one.  long_mode="chunks" keeps the
-    chunked long lane."""
+    long_mode="feed" (the default with a backend that has a feed): each long
+    request goes whole to the backend's persistent kernel as soon as its
+    admission is done (longest first), and is retired when its result row
+    shows its ticket: it neither waits for an iteration to join nor for the
+    longest chunk of one.  long_mode="chunks": long requests advance
+    long_chunk_bytes per iteration on their own stream.  Every lane keeps its
+    own work in flight, so long requests never stretch the short requests'
+    iterations."""
 
     def __init__(self, backend, budget_bytes: int, chunk_bytes: int = 1 << 16,
                  max_active: Optional[int] = None, clock=time.perf_counter,
