@@ -405,9 +405,10 @@ class GpuBackend:
         return None if res is None else res.numpy().view(np.uint64)
 
     def feed_submit(self, slots, arena_offs, lengths, widths) -> int:
-        """Hand one group of admitted requests (at most FEED_GROUP) to the
-        feed; returns the first request's ticket, or 0 if the queue is full.
-        A request's result appears in feed_rows()[slot] with its ticket."""
+        """Hand admitted requests to the feed (taken in this order); returns
+        the first request's ticket (request i: ticket + i), or 0 if the queue
+        has no room for them yet.  A request's result appears in
+        feed_rows()[slot] with its ticket."""
         return self._feed.submit(arena_offs, lengths, self.slot_key[slots], widths, slots)
 
     def feed_rows(self) -> np.ndarray:
