@@ -233,8 +233,10 @@ hh_status hh_copy_segments(uint8_t* dst, uint64_t dst_bytes, const uint8_t* src,
  * that few CUs carry the long chains beside other work.  Each launch stops
  * taking messages after max_ms (1 .. HH_FEED_MAX_MS) milliseconds and ends
  * once it has finished those it holds; hh_feed_submit and hh_feed_poll
- * launch again while submitted messages wait.  Allocates host and device
- * memory (HH_ERR_OUT_OF_MEMORY). */
+ * launch again while submitted messages wait (so a message submitted as a
+ * launch ends waits for the longest message that launch still holds:
+ * choose max_ms well above the longest message's hashing time).  Allocates
+ * host and device memory (HH_ERR_OUT_OF_MEMORY). */
 #define HH_FEED_MAX_SLOTS 65536u
 #define HH_FEED_MAX_WAVES 65u
 #define HH_FEED_MAX_MS 60000u
