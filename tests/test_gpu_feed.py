@@ -189,3 +189,47 @@ def test_bad_arguments_rejected(hh):
         assert feed.rows[:, 4].tolist() == [0, 0]   # nothing was queued
     finally:
         feed.close()
+
+
+def test_ring_wraps_with_slots_recycled(hh):
+    # 8 slots, so the 8-entry queue wraps around dozens of times; each slot
+    # is submitted again as soon as its result is seen (one message per
+    # call, or the queue is momentarily full and the call is repeated)
+    rng = np.random.default_rng(76)
+    n, slots = 300, 8
+    data, offsets, lengths = _buffer(rng, rng.integers(0, 100000, n))
+    keys = rng.integers(0, 2**64, size=(4, 4), dtype=np.uint64)
+    key_idx = rng.integers(0, 4, n).astype(np.uint32)
+    widths = np.array([1, 2, 4], np.uint8)[rng.integers(0, 3, n)]
+    k_t, d_t = dev(keys, torch.int64), dev(data)
+    torch.cuda.synchronize()
+    feed = hh.Feed(k_t, d_t, slots=slots, waves=3, max_ms=2000, stream=torch.cuda.Stream())
+    got = np.zeros((n, 4), np.uint64)
+    owner = [-1] * slots          # message held by each slot
+    ticket = np.zeros(slots, np.uint64)
+    nxt, done, busy_calls = 0, 0, 0
+    t_end = time.monotonic() + 30.0
+    try:
+        announce("feed ring wrap", n, slots)
+        while done < n:
+            assert time.monotonic() < t_end, "results did not arrive"
+            for s in range(slots):
+                j = owner[s]
+                if j >= 0 and feed.rows[s, 4] == ticket[s]:
+                    got[j] = feed.rows[s, :4]
+                    owner[s] = -1
+                    done += 1
+                if owner[s] < 0 and nxt < n:
+                    t = feed.submit(offsets[nxt:nxt + 1], lengths[nxt:nxt + 1],
+                                    key_idx[nxt:nxt + 1], widths[nxt:nxt + 1], np.array([s]))
+                    if t:
+                        owner[s], ticket[s] = nxt, t
+                        nxt += 1
+                    else:
+                        busy_calls += 1
+            feed.poll()
+    finally:
+        feed.close()
+    print("[gpu-case] queue-full retries", busy_calls, flush=True)
+    want = oracle_ref(4, keys, key_idx, data, offsets, lengths)
+    _check(got, want, widths)
