@@ -51,6 +51,7 @@ constexpr u64 kTicksPerMs = 100000;  // the real-time counter runs at 100 MHz
 constexpr u64 kNone = ~0ull;
 constexpr int kFeedRing = 48;            // packets in flight per thread
 constexpr u32 kRoundPackets = 2048;      // packets per message between two looks at the queue
+constexpr u32 kFullRoundPackets = 8192;  // at most this many in a round of a wave with no free place
 
 struct FeedReq {
     u64 offset, length, ticket;
@@ -107,6 +108,15 @@ __device__ __forceinline__ void sys_store(u64* p, u64 v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ u64 ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+__device__ __forceinline__ u64 wave_min(u64 v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const u64 o = __shfl_xor(v, d);
+        v = o < v ? o : v;
+    }
+    return v;
+}
 
 __device__ __forceinline__ u64 wave_broadcast(u64 v) {
     const u32 lo = (u32)__builtin_amdgcn_readfirstlane((int)(u32)v);
@@ -230,10 +240,20 @@ __global__ __launch_bounds__(64) void hh_feed_kernel(FeedArgs a) {
             __builtin_amdgcn_s_sleep(32);
             continue;
         }
-        // one round: every quad with whole packets left absorbs up to
-        // kRoundPackets of them
+        // one round: every quad with whole packets left absorbs up to `round`
+        // of them.  A wave with a free place looks at the queue every
+        // kRoundPackets; a full wave cannot take a message, so its round runs
+        // on to the first of its messages to finish (at most
+        // kFullRoundPackets): each round restarts the prefetch ring, and a
+        // message's result is written at the end of the round that finishes it
+        u64 round = kRoundPackets;
+        if (!__ballot(q == 0 && !active)) {
+            const u64 first_done = wave_min(active && rem ? rem : ~0ull);
+            round = first_done < kRoundPackets ? kRoundPackets
+                    : (first_done > kFullRoundPackets ? kFullRoundPackets : first_done);
+        }
         if (active && rem) {
-            const u32 npk = (u32)(rem < kRoundPackets ? rem : kRoundPackets);
+            const u32 npk = (u32)(rem < round ? rem : round);
             absorb_quad<kFeedRing>(s, p + 8u * (u32)q, npk);
             p += 32u * (u64)npk;
             rem -= npk;
