@@ -595,13 +595,18 @@ def main(argv=None) -> int:
     serving_check = None
     if not args.no_serving:
         from paper_1612_06257_amd import serve
-        summary, trace, results = serve.bench_summary()
-        result["serving"] = summary
-        serving_check = (trace, results)
-        pts = [summary["saturation"]] + summary["loads"]
-        print("[bench] serving: %s" % json.dumps(
-            [{"load": v["load"], "GBps": round(v["GBps"], 1), "p50_ms": round(v["p50_ms"], 3),
-              "p99_ms": round(v["p99_ms"], 2)} for v in pts]), file=sys.stderr, flush=True)
+        try:
+            summary, trace, results = serve.bench_summary()
+        except RuntimeError as e:  # a stalled loop: report it, keep the rest of the line
+            result["serving"] = {"error": str(e)}
+            print("[bench] serving failed: %s" % e, file=sys.stderr, flush=True)
+        else:
+            result["serving"] = summary
+            serving_check = (trace, results)
+            pts = [summary["saturation"]] + summary["loads"]
+            print("[bench] serving: %s" % json.dumps(
+                [{"load": v["load"], "GBps": round(v["GBps"], 1), "p50_ms": round(v["p50_ms"], 3),
+                  "p99_ms": round(v["p99_ms"], 2)} for v in pts]), file=sys.stderr, flush=True)
 
     if not args.no_plain and width == 1:
         plain, plain_hash = time_plain(hh, b, dev)
@@ -627,7 +632,8 @@ def main(argv=None) -> int:
 
     print(json.dumps(result))
     ok = (result.get("parity", "bit-exact") == "bit-exact"
-          and (result["serving"] or {}).get("parity", "bit-exact") == "bit-exact")
+          and (result["serving"] or {}).get("parity", "bit-exact") == "bit-exact"
+          and "error" not in (result["serving"] or {}))
     return 0 if ok else 3
 
 

@@ -444,7 +444,8 @@ class Server:
                  max_active: Optional[int] = None, clock=time.perf_counter,
                  sleep=time.sleep, run_ahead: int = 2, long_chunk_bytes: int = 1 << 20,
                  long_min_bytes: Optional[int] = None, poll_s: float = 5e-4,
-                 long_mode: Optional[str] = None, feed_poll_s: float = 5e-5):
+                 long_mode: Optional[str] = None, feed_poll_s: float = 5e-5,
+                 stall_s: float = 60.0):
         for c in (chunk_bytes, long_chunk_bytes):
             if c <= 0 or c % 32:
                 raise ValueError("chunk sizes must be positive multiples of 32")
@@ -469,6 +470,8 @@ class Server:
             long_min_bytes = (4 if long_mode == "feed" else 16) * chunk_bytes
         self.long_min = long_min_bytes
         self.feed_poll_s = feed_poll_s
+        # the loop raises when admitted work makes no progress for this long
+        self.stall_s = stall_s
         self.arena = Arena(budget_bytes)
         self.max_active = max_active or backend.max_slots
         self.free_slots = list(range(backend.max_slots))[::-1]
@@ -570,8 +573,15 @@ class Server:
             self.free_slots.extend(fin.tolist())
             self.n_finished += len(fin)
 
+        last_progress, seen_finished = 0.0, 0
         while self.n_finished < n_total:
             now = self.clock() - t0
+            if self.n_finished != seen_finished or not (n_busy or n_fed or any(inflight) or gated):
+                last_progress, seen_finished = now, self.n_finished
+            elif now - last_progress > self.stall_s:
+                raise RuntimeError("serving loop: no request finished for %.1f s with %d in "
+                                   "flight" % (now - last_progress,
+                                               n_busy + n_fed + len(gated)))
             arrived = int(np.searchsorted(arrival, now, side="right"))
             # admission, in arrival order, while a slot and budget are free
             runs = []

@@ -205,3 +205,23 @@ def test_chunked_long_lane_still_selectable():
     with pytest.raises(ValueError):
         serve.Server(CpuBackend(tr.keys, tr.data, 1 << 17, 64, clock), budget_bytes=1 << 17,
                      long_mode="feed")
+
+
+def test_stalled_loop_raises():
+    # a feed whose results never appear: the loop gives up after stall_s of
+    # virtual time instead of polling for ever
+    from _serve_cpu import FeedCpuBackend
+
+    class Stuck(FeedCpuBackend):
+        def feed_submit(self, slots, arena_offs, lengths, widths):
+            t = self.next_ticket
+            self.next_ticket += len(slots)
+            return t
+
+    tr = _trace(40, 1000.0, hi=9000, seed=61)
+    clock = VirtualClock()
+    be = Stuck(tr.keys, tr.data, 1 << 18, 64, clock)
+    srv = serve.Server(be, budget_bytes=1 << 18, chunk_bytes=64, long_min_bytes=2048,
+                       clock=clock, sleep=clock.sleep, stall_s=0.5)
+    with pytest.raises(RuntimeError, match="no request finished"):
+        srv.run(serve.requests_from_trace(tr))
