@@ -236,12 +236,16 @@ class GpuBackend:
             self._warm_stream(self.copy_stream)
         self.launcher.submit(self._warm_stream, self.lane_streams[1]).result()
         # the long requests' feed: a persistent kernel on the lane 1 stream
-        # that hashes each long request whole from the arena; it launches on
-        # the first submitted group, so a chunked long lane keeps that
-        # stream to itself
+        # that hashes each long request whole; it launches on the first
+        # submitted request, so a chunked long lane keeps that stream to
+        # itself.  With device ingress it reads the requests where they
+        # arrived (feed_reads_source: no admission copy to wait for; the
+        # budget still reserves their bytes), with host ingress from the arena
+        # once admission has copied them there.
         self.slot_key = np.zeros(max_slots, np.uint32)
-        self._feed = hh.Feed(self.keys, self.arena, max_slots, feed_waves, feed_max_ms,
-                             self.lane_streams[1])
+        self.feed_reads_source = source == "device"
+        self._feed = hh.Feed(self.keys, self.ingress if self.feed_reads_source else self.arena,
+                             max_slots, feed_waves, feed_max_ms, self.lane_streams[1])
 
     def _warm_stream(self, stream) -> None:
         with self.torch.cuda.stream(stream):
@@ -404,12 +408,12 @@ class GpuBackend:
         ev, res = self._resolve(ticket)
         return None if res is None else res.numpy().view(np.uint64)
 
-    def feed_submit(self, slots, arena_offs, lengths, widths) -> int:
+    def feed_submit(self, slots, offsets, lengths, widths, key_idx) -> int:
         """Hand admitted requests to the feed (taken in this order); returns
         the first request's ticket (request i: ticket + i), or 0 if the queue
         has no room for them yet.  A request's result appears in
         feed_rows()[slot] with its ticket."""
-        return self._feed.submit(arena_offs, lengths, self.slot_key[slots], widths, slots)
+        return self._feed.submit(offsets, lengths, key_idx, widths, slots)
 
     def feed_rows(self) -> np.ndarray:
         """(max_slots, 5) uint64: hash words, then the ticket they belong to."""
@@ -541,6 +545,11 @@ class Server:
         inflight = [collections.deque() for _ in range(self.lanes)]
         feed = self.long_mode == "feed"
         fed = np.zeros(S, bool)             # handed to the feed, result not yet seen
+        src_off = np.zeros(S, np.int64)     # ingress offset of the slot's request
+        key_of = np.zeros(S, np.int64)      # key index of the slot's request
+        # with device ingress the feed reads a request where it arrived: the
+        # request needs no admission copy and is ready at once
+        direct = feed and getattr(self.backend, "feed_reads_source", False)
         fticket = np.zeros(S, np.uint64)    # the feed ticket of that request
         n_fed = 0
         self.feed_submits = 0
@@ -618,6 +627,7 @@ class Server:
                 busy[slots], length[slots], pos[slots] = True, r_len[ridx], 0
                 base[slots], resv[slots], width[slots] = offs, need[:k], r_width[ridx]
                 owner[slots] = ridx
+                src_off[slots], key_of[slots] = r_src[ridx], r_key[ridx]
                 lane[slots] = (r_len[ridx] > self.long_min) if self.lanes > 1 else 0
                 self.reserved_bytes += int(need[:k].sum())
                 n_busy += k
@@ -627,12 +637,18 @@ class Server:
             adm = None
             if runs:
                 ridx = np.concatenate(runs)
-                adm = self.backend.admit(AdmitBatch(src=r_src[ridx], arena_off=r_off[ridx],
-                                                    length=r_len[ridx], key_idx=r_key[ridx],
-                                                    slot=r_slot[ridx]))
-                if self.lanes > 1:
-                    longs = r_slot[ridx][lane[r_slot[ridx]] == 1]
-                    if longs.size:
+                is_long = (lane[r_slot[ridx]] == 1) if self.lanes > 1 else np.zeros(0, bool)
+                if direct:
+                    # long requests skip admission: the feed reads their bytes
+                    # where they arrived, so they are ready at once
+                    ridx = ridx[~is_long]
+                    is_long = is_long[~is_long]
+                if ridx.size:
+                    adm = self.backend.admit(AdmitBatch(src=r_src[ridx], arena_off=r_off[ridx],
+                                                        length=r_len[ridx], key_idx=r_key[ridx],
+                                                        slot=r_slot[ridx]))
+                    if is_long.any():
+                        longs = r_slot[ridx][is_long]
                         ready[longs] = False
                         gated.append((adm, longs))
             # long-lane requests whose admission has completed may advance
@@ -644,7 +660,8 @@ class Server:
                 g = np.flatnonzero(busy & (lane == 1) & ready)
                 if g.size:
                     g = g[np.argsort(-length[g], kind="stable")]
-                    tk = self.backend.feed_submit(g, base[g], length[g], width[g])
+                    tk = self.backend.feed_submit(g, src_off[g] if direct else base[g],
+                                                  length[g], width[g], key_of[g])
                     if tk:  # else the queue is full: they wait for the next pass
                         fticket[g] = tk + np.arange(g.size, dtype=np.uint64)
                         fed[g] = True

@@ -93,28 +93,37 @@ class CpuBackend:
 class FeedCpuBackend(CpuBackend):
     """CpuBackend with a feed: submitted requests are hashed whole at once
     (the longest one's cost advances the clock) and their rows show the
-    results and tickets."""
+    results and tickets.  reads_source: the feed hashes a request from the
+    payload where it arrived (the server then skips its admission); else
+    from the arena after admission."""
     FEED = True
 
-    def __init__(self, *args, **kw):
+    def __init__(self, *args, reads_source=False, **kw):
         super().__init__(*args, **kw)
+        self.feed_reads_source = reads_source
         self.rows = np.zeros((self.max_slots, 5), np.uint64)
         self.next_ticket = 1
         self.submits = []   # (slots, lengths) per submit call
 
-    def feed_submit(self, slots, arena_offs, lengths, widths):
+    def feed_submit(self, slots, offsets, lengths, widths, key_idx):
         assert len(slots) >= 1
         t = self.next_ticket
         self.next_ticket += len(slots)
         self.submits.append((np.asarray(slots).copy(), np.asarray(lengths).copy()))
-        for i, (slot, off, n) in enumerate(zip(np.asarray(slots).tolist(),
-                                               np.asarray(arena_offs).tolist(),
-                                               np.asarray(lengths).tolist())):
-            c = self.cats.pop(slot)
-            c.append(self.arena[off:off + n])
+        for i, (slot, off, n, k) in enumerate(zip(np.asarray(slots).tolist(),
+                                                  np.asarray(offsets).tolist(),
+                                                  np.asarray(lengths).tolist(),
+                                                  np.asarray(key_idx).tolist())):
+            if self.feed_reads_source:
+                assert slot not in self.cats  # the server skipped its admission
+                c = oracle.Cat(self.keys[k])
+                c.append(self.payload[off:off + n])
+            else:
+                c = self.cats.pop(slot)
+                c.append(self.arena[off:off + n])
+                del self.live[slot]
             self.rows[slot, :4] = c.finish(4)
             self.rows[slot, 4] = t + i
-            del self.live[slot]
         self.clock.t += self.launch_s + max(np.asarray(lengths).tolist()) * self.ns_per_byte * 1e-9
         return t
 

@@ -166,14 +166,16 @@ def test_collector_off_during_the_loop_and_restored():
             gc.enable()
 
 
-def test_feed_mode_results_equal_one_shot():
-    # long requests go whole to the feed, longest first, each exactly once;
+@pytest.mark.parametrize("reads_source", [False, True])
+def test_feed_mode_results_equal_one_shot(reads_source):
+    # long requests go whole to the feed, longest first, each exactly once,
+    # from the arena after admission or straight from where they arrived;
     # every result is exact
     from _serve_cpu import FeedCpuBackend
     tr = _trace(300, 3000.0, hi=9000, seed=51)
     clock = VirtualClock()
     reqs = serve.requests_from_trace(tr)
-    be = FeedCpuBackend(tr.keys, tr.data, 1 << 18, 128, clock)
+    be = FeedCpuBackend(tr.keys, tr.data, 1 << 18, 128, clock, reads_source=reads_source)
     srv = serve.Server(be, budget_bytes=1 << 18, chunk_bytes=64, long_min_bytes=2048,
                        clock=clock, sleep=clock.sleep)
     assert srv.long_mode == "feed"
@@ -213,7 +215,7 @@ def test_stalled_loop_raises():
     from _serve_cpu import FeedCpuBackend
 
     class Stuck(FeedCpuBackend):
-        def feed_submit(self, slots, arena_offs, lengths, widths):
+        def feed_submit(self, slots, offsets, lengths, widths, key_idx):
             t = self.next_ticket
             self.next_ticket += len(slots)
             return t
