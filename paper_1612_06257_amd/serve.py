@@ -149,10 +149,10 @@ class GpuBackend:
     """Device side of the loop: payload arena, states, outputs, launches.
 
     source="device": the trace's payloads sit in a device ingress buffer and
-    admission moves all of an iteration's payloads into the arena with one
-    segment-copy launch on the compute stream;
+    the kernels read each request where it arrived (the arena is then only
+    the budget's bookkeeping);
     source="host": they sit in pinned host memory and admission copies them
-    host to device on a copy stream that the compute stream waits for.
+    into the arena on a copy stream that the compute stream waits for.
     Admission resets the new states in place.  Per-iteration item lists go
     through a ring of pinned staging buffers so that no copy waits for the
     host, and finished hashes are written compacted in launch order so that
@@ -235,17 +235,19 @@ class GpuBackend:
         if source == "host":
             self._warm_stream(self.copy_stream)
         self.launcher.submit(self._warm_stream, self.lane_streams[1]).result()
+        # With device ingress every kernel reads a request where it arrived
+        # (reads_source: admission only resets states, there is no copy to
+        # wait for; the budget still reserves the requests' bytes); with host
+        # ingress they read the arena once admission has copied them there.
+        self.reads_source = source == "device"
+        self.data = self.ingress if self.reads_source else self.arena
         # the long requests' feed: a persistent kernel on the lane 1 stream
         # that hashes each long request whole; it launches on the first
         # submitted request, so a chunked long lane keeps that stream to
-        # itself.  With device ingress it reads the requests where they
-        # arrived (feed_reads_source: no admission copy to wait for; the
-        # budget still reserves their bytes), with host ingress from the arena
-        # once admission has copied them there.
+        # itself
         self.slot_key = np.zeros(max_slots, np.uint32)
-        self.feed_reads_source = source == "device"
-        self._feed = hh.Feed(self.keys, self.ingress if self.feed_reads_source else self.arena,
-                             max_slots, feed_waves, feed_max_ms, self.lane_streams[1])
+        self._feed = hh.Feed(self.keys, self.data, max_slots, feed_waves, feed_max_ms,
+                             self.lane_streams[1])
 
     def _warm_stream(self, stream) -> None:
         with self.torch.cuda.stream(stream):
@@ -287,12 +289,8 @@ class GpuBackend:
         self.slot_key[batch.slot] = batch.key_idx
         d = self.d_adm[lane][i]
         d[:32 * n].copy_(self.h_adm[lane][i][:32 * n], non_blocking=True)
-        if self.source == "device":
-            # one launch moves every payload, in stream order before the
-            # lane's next iteration
-            self.hh.copy_segments(self.arena, self.ingress, d[:8 * n].view(torch.int64),
-                                  d[8 * n:16 * n].view(torch.int64),
-                                  d[16 * n:24 * n].view(torch.int64), int(lens.max()))
+        if self.reads_source:
+            pass  # the kernels read the payloads where they arrived
         else:
             with torch.cuda.stream(self.copy_stream):
                 for so, do, ln in zip(batch.src.tolist(), batch.arena_off.tolist(),
@@ -362,7 +360,7 @@ class GpuBackend:
                 # set: its stream carries no copies (a copy queued behind a
                 # long iteration could hold up the host)
                 mb = self.meta_dev[lane][i]
-                hh.state_step_raw(self.states, self.arena, mb + regs["o"][0], mb + regs["l"][0],
+                hh.state_step_raw(self.states, self.data, mb + regs["o"][0], mb + regs["l"][0],
                                   mb + regs["w"][0], self.res_dev[lane][i],
                                   self.max_slots * 4, mb + regs["oo"][0], mb + regs["s"][0], n,
                                   self.lane_streams[lane].cuda_stream)
@@ -377,7 +375,7 @@ class GpuBackend:
                     return d[o:o + nb].view(dt)
 
                 out = self.out[lane]
-                hh.state_step(self.states, self.arena, view("o", torch.int64),
+                hh.state_step(self.states, self.data, view("o", torch.int64),
                               view("l", torch.int64), view("w", torch.uint8), out.view(-1),
                               view("oo", torch.int64), view("s", torch.int32))
                 if n_fin:
@@ -409,10 +407,11 @@ class GpuBackend:
         return None if res is None else res.numpy().view(np.uint64)
 
     def feed_submit(self, slots, offsets, lengths, widths, key_idx) -> int:
-        """Hand admitted requests to the feed (taken in this order); returns
-        the first request's ticket (request i: ticket + i), or 0 if the queue
-        has no room for them yet.  A request's result appears in
-        feed_rows()[slot] with its ticket."""
+        """Hand admitted requests to the feed (taken in this order; offsets
+        into self.data, the buffer the kernels read); returns the first
+        request's ticket (request i: ticket + i), or 0 if the queue has no
+        room for them yet.  A request's result appears in feed_rows()[slot]
+        with its ticket."""
         return self._feed.submit(offsets, lengths, key_idx, widths, slots)
 
     def feed_rows(self) -> np.ndarray:
@@ -534,7 +533,8 @@ class Server:
         busy = np.zeros(S, bool)          # admitted, final not yet launched
         length = np.zeros(S, np.int64)
         pos = np.zeros(S, np.int64)
-        base = np.zeros(S, np.int64)      # arena offset
+        base = np.zeros(S, np.int64)      # offset of the payload in the buffer the kernels read
+        held = np.zeros(S, np.int64)      # arena offset of the reservation
         resv = np.zeros(S, np.int64)      # budget bytes held
         width = np.zeros(S, np.uint8)
         owner = np.full(S, -1, np.int64)  # request in the slot
@@ -545,11 +545,12 @@ class Server:
         inflight = [collections.deque() for _ in range(self.lanes)]
         feed = self.long_mode == "feed"
         fed = np.zeros(S, bool)             # handed to the feed, result not yet seen
-        src_off = np.zeros(S, np.int64)     # ingress offset of the slot's request
         key_of = np.zeros(S, np.int64)      # key index of the slot's request
-        # with device ingress the feed reads a request where it arrived: the
-        # request needs no admission copy and is ready at once
-        direct = feed and getattr(self.backend, "feed_reads_source", False)
+        # with device ingress the kernels read a request where it arrived
+        # (offsets into the ingress buffer), and a feed request needs no
+        # admission at all: it is ready at once
+        in_place = getattr(self.backend, "reads_source", False)
+        direct = feed and in_place
         fticket = np.zeros(S, np.uint64)    # the feed ticket of that request
         n_fed = 0
         self.feed_submits = 0
@@ -576,7 +577,7 @@ class Server:
             t_done[ridx] = t
             status[ridx] = 2
             owner[fin] = -1
-            self.arena.release_many(list(zip(base[fin].tolist(),
+            self.arena.release_many(list(zip(held[fin].tolist(),
                                              np.maximum(length[fin], 1).tolist())))
             self.reserved_bytes -= int(resv[fin].sum())
             self.free_slots.extend(fin.tolist())
@@ -625,9 +626,10 @@ class Server:
                 status[ridx], r_slot[ridx], r_off[ridx] = 1, slots, offs
                 r_resv[ridx], t_admit[ridx] = need[:k], now
                 busy[slots], length[slots], pos[slots] = True, r_len[ridx], 0
-                base[slots], resv[slots], width[slots] = offs, need[:k], r_width[ridx]
+                base[slots] = r_src[ridx] if in_place else offs
+                held[slots], resv[slots], width[slots] = offs, need[:k], r_width[ridx]
                 owner[slots] = ridx
-                src_off[slots], key_of[slots] = r_src[ridx], r_key[ridx]
+                key_of[slots] = r_key[ridx]
                 lane[slots] = (r_len[ridx] > self.long_min) if self.lanes > 1 else 0
                 self.reserved_bytes += int(need[:k].sum())
                 n_busy += k
@@ -660,7 +662,7 @@ class Server:
                 g = np.flatnonzero(busy & (lane == 1) & ready)
                 if g.size:
                     g = g[np.argsort(-length[g], kind="stable")]
-                    tk = self.backend.feed_submit(g, src_off[g] if direct else base[g],
+                    tk = self.backend.feed_submit(g, base[g],
                                                   length[g], width[g], key_of[g])
                     if tk:  # else the queue is full: they wait for the next pass
                         fticket[g] = tk + np.arange(g.size, dtype=np.uint64)

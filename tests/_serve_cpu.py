@@ -25,7 +25,7 @@ class CpuBackend:
     LANES = 2
 
     def __init__(self, keys, payload, arena_bytes, max_slots, clock, ns_per_byte=0.05,
-                 launch_s=20e-6):
+                 launch_s=20e-6, reads_source=False):
         self.keys = np.asarray(keys, np.uint64).reshape(-1, 4)
         self.payload = payload
         self.arena = np.zeros(max(arena_bytes, 256), np.uint8)
@@ -38,6 +38,10 @@ class CpuBackend:
         self.launches = 0
         self.lane_launches = [0, 0]
         self.lane_of = {}  # slot -> lane of its first launch
+        # reads_source: the kernels read requests where they arrived (offsets
+        # into the payload), admission copies nothing
+        self.reads_source = reads_source
+        self.data = payload if reads_source else self.arena
 
     def _check_no_overlap(self):
         spans = sorted((o, o + max(n, 1)) for o, n in self.live.values())
@@ -49,7 +53,8 @@ class CpuBackend:
                                           batch.length.tolist(), batch.key_idx.tolist(),
                                           batch.slot.tolist()):
             assert slot not in self.cats, "slot reused while live"
-            self.arena[off:off + n] = self.payload[src:src + n]
+            if not self.reads_source:
+                self.arena[off:off + n] = self.payload[src:src + n]
             self.cats[slot] = oracle.Cat(self.keys[key])
             self.live[slot] = (off, n)
         self._check_no_overlap()
@@ -67,13 +72,13 @@ class CpuBackend:
         biggest = 0
         for slot, off, n in zip(upd_slots.tolist(), upd_offs.tolist(), upd_lens.tolist()):
             assert n % 32 == 0
-            self.cats[slot].append(self.arena[off:off + n])
+            self.cats[slot].append(self.data[off:off + n])
             biggest = max(biggest, n)
         res = np.zeros((len(fin_slots), 4), np.uint64)
         for i, (slot, off, n) in enumerate(zip(fin_slots.tolist(), fin_offs.tolist(),
                                                fin_lens.tolist())):
             c = self.cats.pop(slot)
-            c.append(self.arena[off:off + n])
+            c.append(self.data[off:off + n])
             res[i] = c.finish(4)
             del self.live[slot]
             biggest = max(biggest, n)
@@ -98,9 +103,8 @@ class FeedCpuBackend(CpuBackend):
     from the arena after admission."""
     FEED = True
 
-    def __init__(self, *args, reads_source=False, **kw):
+    def __init__(self, *args, **kw):
         super().__init__(*args, **kw)
-        self.feed_reads_source = reads_source
         self.rows = np.zeros((self.max_slots, 5), np.uint64)
         self.next_ticket = 1
         self.submits = []   # (slots, lengths) per submit call
@@ -114,14 +118,13 @@ class FeedCpuBackend(CpuBackend):
                                                   np.asarray(offsets).tolist(),
                                                   np.asarray(lengths).tolist(),
                                                   np.asarray(key_idx).tolist())):
-            if self.feed_reads_source:
+            if self.reads_source:
                 assert slot not in self.cats  # the server skipped its admission
                 c = oracle.Cat(self.keys[k])
-                c.append(self.payload[off:off + n])
             else:
                 c = self.cats.pop(slot)
-                c.append(self.arena[off:off + n])
                 del self.live[slot]
+            c.append(self.data[off:off + n])
             self.rows[slot, :4] = c.finish(4)
             self.rows[slot, 4] = t + i
         self.clock.t += self.launch_s + max(np.asarray(lengths).tolist()) * self.ns_per_byte * 1e-9

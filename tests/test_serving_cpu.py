@@ -16,11 +16,11 @@ def _trace(n, rate, hi, seed=7):
     return tr
 
 
-def _run(tr, budget, chunk, max_slots=64):
+def _run(tr, budget, chunk, max_slots=64, reads_source=False):
     clock = VirtualClock()
     reqs = serve.requests_from_trace(tr)
     arena = budget
-    be = CpuBackend(tr.keys, tr.data, arena, max_slots, clock)
+    be = CpuBackend(tr.keys, tr.data, arena, max_slots, clock, reads_source=reads_source)
     srv = serve.Server(be, budget_bytes=budget, chunk_bytes=chunk, clock=clock, sleep=clock.sleep)
     m = srv.run(reqs)
     return m, reqs, be
@@ -75,10 +75,13 @@ def test_arena_batched_release_equals_one_by_one():
     assert a.free == [(0, a.capacity)] and a.used == 0
 
 
-@pytest.mark.parametrize("chunk", [32, 256, 4096])
-def test_results_equal_one_shot_hashes(chunk):
+@pytest.mark.parametrize("chunk,reads_source", [(32, False), (256, False), (4096, False),
+                                                (256, True)])
+def test_results_equal_one_shot_hashes(chunk, reads_source):
+    # reads_source: the kernels read each request where it arrived (device
+    # ingress); the arena then only keeps the budget's books
     tr = _trace(250, 2000.0, hi=6000)
-    m, reqs, be = _run(tr, budget=1 << 16, chunk=chunk)
+    m, reqs, be = _run(tr, budget=1 << 16, chunk=chunk, reads_source=reads_source)
     assert m["completed"] + m["rejected"] == len(reqs)
     assert m["rejected"] == 0
     for r in reqs:
