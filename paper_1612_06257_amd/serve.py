@@ -639,7 +639,8 @@ class Server:
             adm = None
             if runs:
                 ridx = np.concatenate(runs)
-                is_long = (lane[r_slot[ridx]] == 1) if self.lanes > 1 else np.zeros(ridx.size, bool)
+                is_long = ((lane[r_slot[ridx]] == 1) if self.lanes > 1
+                           else np.zeros(ridx.size, bool))
                 if direct:
                     # long requests skip admission: the feed reads their bytes
                     # where they arrived, so they are ready at once
