@@ -29,7 +29,7 @@ def kernel_stats(path, out, command):
     lines = ["# rocprofv3 --kernel-trace --stats", "", "Command: `%s`" % command, "",
              "| kernel | calls | avg us | min us | max us | % |", "|---|---|---|---|---|---|"]
     for r in rows:
-        name = r["Name"].split("(")[0].replace("void ", "")
+        name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         lines.append("| %s | %s | %.1f | %.1f | %.1f | %.2f |" % (
             name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
             float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
@@ -44,7 +44,8 @@ def _base(kernel: str) -> str:
 def _per_kernel(path):
     agg = {}
     for r in csv.DictReader(open(path)):
-        agg.setdefault(r["Kernel_Name"].split("(")[0].replace("void ", ""), []).append(
+        name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+        agg.setdefault(name.split("(")[0].replace("void ", ""), []).append(
             float(r["Counter_Value"]))
     return {k: sum(v) / len(v) for k, v in agg.items()}
 
