@@ -656,6 +656,21 @@ def state_step_raw(states: torch.Tensor, data: torch.Tensor, offsets: int, lengt
                                _vp(out), out_words, _vp(out_offsets), n, _vp(stream)))
 
 
+def state_init_raw(keys: torch.Tensor, n: int, key_idx: int, states: torch.Tensor,
+                   state_idx: int, stream: int) -> None:
+    """state_init with key_idx and state_idx given as device addresses (e.g.
+    from pinned_device_pointer) and an explicit stream handle; keys and
+    states are device tensors as for state_init."""
+    _dev(keys, "keys", _W64, 2)
+    _dev(states, "states", _W64, 2)
+    if not (key_idx and state_idx):
+        raise ValueError("key_idx and state_idx must be given")
+    if states.shape[1] != STATE_WORDS:
+        raise ValueError("states must have shape (rows, 16)")
+    _check(lib().hh_state_init(_ptr(keys), keys.shape[0], _vp(key_idx), _ptr(states),
+                               states.shape[0], _vp(state_idx), n, _vp(stream)))
+
+
 def timing_enable(on: bool = True) -> None:
     """Record HIP events around each bucketed call's long-message kernel."""
     _check(lib().hh_timing_enable(int(bool(on))))

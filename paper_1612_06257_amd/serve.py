@@ -33,6 +33,7 @@ import argparse
 import bisect
 import collections
 import concurrent.futures
+import ctypes
 import dataclasses
 import gc
 import json
@@ -45,6 +46,21 @@ import numpy as np
 STATE_BYTES = 128
 OUT_BYTES = 32
 GRANULE = 256
+
+
+def _timer_slack(ns: int) -> int:
+    """Set the calling thread's timer slack (Linux prctl) to ns nanoseconds;
+    returns the previous value, or -1 where it cannot be read or set.  With
+    the default slack of 50 us a sleep of a few microseconds lasted 55-100 us,
+    which the serving loop's short sleeps added to every request in flight."""
+    try:
+        libc = ctypes.CDLL(None, use_errno=True)
+        prev = libc.prctl(30, 0, 0, 0, 0)          # PR_GET_TIMERSLACK
+        if prev < 0 or libc.prctl(29, ctypes.c_ulong(ns), 0, 0, 0) != 0:  # PR_SET_TIMERSLACK
+            return -1
+        return prev
+    except (OSError, AttributeError):
+        return -1
 
 
 @dataclasses.dataclass
@@ -153,15 +169,16 @@ class GpuBackend:
     the budget's bookkeeping);
     source="host": they sit in pinned host memory and admission copies them
     into the arena on a copy stream that the compute stream waits for.
-    Admission resets the new states in place.  Per-iteration item lists go
-    through a ring of pinned staging buffers so that no copy waits for the
-    host, and finished hashes are written compacted in launch order so that
-    one contiguous copy brings them back.
+    Admission resets the new states in place.  Admission and iteration item
+    lists go through rings of pinned staging sets that the kernels read
+    where they are, and an iteration writes its finished hashes, compacted
+    in launch order, straight into a pinned result set: no stream carries a
+    copy for them, and a launch costs the host one kernel call and one event.
 
     Two lanes: lane 0 launches on the compute stream, lane 1 (the long
-    requests' lane) on a stream of its own with its own staging ring and
-    output buffer, so that a long lane iteration never holds up the short
-    requests' iterations.  Admission runs on the compute stream; the lane 1
+    requests' lane) on a stream of its own with its own staging and result
+    sets, so that a long lane iteration never holds up the short requests'
+    iterations.  Admission runs on the compute stream; the lane 1
     stream only ever receives that lane's iterations, or the feed's
     persistent kernel (feed_submit), which hashes a long request whole and
     writes its result into host memory."""
@@ -179,8 +196,6 @@ class GpuBackend:
         self.keys = torch.from_numpy(np.ascontiguousarray(keys)).view(torch.int64).cuda()
         self.max_slots = max_slots
         self.states = torch.zeros((max_slots, hh.STATE_WORDS), dtype=torch.int64, device="cuda")
-        self.out = [torch.zeros((max_slots, 4), dtype=torch.int64, device="cuda")
-                    for _ in range(self.LANES)]
         self.arena = torch.empty(max(arena_bytes, GRANULE), dtype=torch.uint8, device="cuda")
         self.source = source
         src = torch.from_numpy(np.ascontiguousarray(payload))
@@ -205,23 +220,25 @@ class GpuBackend:
         self.meta_bytes = max_slots * (8 + 8 + 8 + 4 + 1) + 64
         self.h_meta = [[torch.empty(self.meta_bytes, dtype=torch.uint8, pin_memory=True)
                         for _ in range(self.RING)] for _ in range(self.LANES)]
-        self.d_meta = [[torch.empty(self.meta_bytes, dtype=torch.uint8, device="cuda")
-                        for _ in range(self.RING)] for _ in range(self.LANES)]
         self.h_res = [[torch.empty((max_slots, 4), dtype=torch.int64, pin_memory=True)
                        for _ in range(self.RING)] for _ in range(self.LANES)]
         # admission metadata per staging set: src offs u64, arena offs u64,
         # lens u64, key index u32, slot u32
         self.adm_bytes = max_slots * 32
-        self.h_adm = [[torch.empty(self.adm_bytes, dtype=torch.uint8, pin_memory=True)
-                       for _ in range(self.RING)] for _ in range(self.LANES)]
-        self.d_adm = [[torch.empty(self.adm_bytes, dtype=torch.uint8, device="cuda")
-                       for _ in range(self.RING)] for _ in range(self.LANES)]
+        self.h_adm = [torch.empty(self.adm_bytes, dtype=torch.uint8, pin_memory=True)
+                      for _ in range(self.RING)]
         self.k = [0] * self.LANES
-        self.ka = [0] * self.LANES
-        # device addresses of the pinned staging and result sets (lane 1
-        # kernels access them directly; lane 0 copies them)
+        self.ka = 0
+        # the kernels read the staging sets and write the result sets where
+        # they are, in pinned host memory (no copies on the streams, and less
+        # host time per launch than torch copies and views): their device
+        # addresses, and numpy views for the host's side
         self.meta_dev = [[hh.pinned_device_pointer(t) for t in ring] for ring in self.h_meta]
         self.res_dev = [[hh.pinned_device_pointer(t) for t in ring] for ring in self.h_res]
+        self.adm_dev = [hh.pinned_device_pointer(t) for t in self.h_adm]
+        self.meta_np = [[t.numpy() for t in ring] for ring in self.h_meta]
+        self.res_np = [[t.numpy().view(np.uint64) for t in ring] for ring in self.h_res]
+        self.adm_np = [t.numpy() for t in self.h_adm]
         self.launcher = concurrent.futures.ThreadPoolExecutor(max_workers=1)
         self.events = [[torch.cuda.Event() for _ in range(self.RING)] for _ in range(self.LANES)]
         self.adm_events = [torch.cuda.Event() for _ in range(self.RING)]
@@ -264,22 +281,14 @@ class GpuBackend:
         now and then)."""
         if batch.n == 0:
             return None
-        i = self.ka[0] % self.RING  # the staging set _admit is about to use
+        i = self.ka % self.RING
+        self.ka += 1
         # that set's previous admission has finished reading it (normally long
         # ago; an event never recorded counts as complete)
         self.adm_events[i].synchronize()
-        self._admit(0, batch)
-        ev = self.adm_events[i]
-        ev.record(self.compute_stream)
-        return (ev, None)
-
-    def _admit(self, lane: int, batch: AdmitBatch) -> None:
-        """Admission work on the current stream, staging ring of `lane`."""
         torch = self.torch
         n = batch.n
-        i = self.ka[lane] % self.RING
-        self.ka[lane] += 1
-        h = self.h_adm[lane][i].numpy()
+        h = self.adm_np[i]
         lens = batch.length
         h[:8 * n].view(np.int64)[:] = batch.src
         h[8 * n:16 * n].view(np.int64)[:] = batch.arena_off
@@ -287,11 +296,9 @@ class GpuBackend:
         h[24 * n:28 * n].view(np.int32)[:] = batch.key_idx
         h[28 * n:32 * n].view(np.int32)[:] = batch.slot
         self.slot_key[batch.slot] = batch.key_idx
-        d = self.d_adm[lane][i]
-        d[:32 * n].copy_(self.h_adm[lane][i][:32 * n], non_blocking=True)
-        if self.reads_source:
-            pass  # the kernels read the payloads where they arrived
-        else:
+        if not self.reads_source:
+            # host ingress: the payloads go to the arena on the copy stream,
+            # which the compute stream waits for
             with torch.cuda.stream(self.copy_stream):
                 for so, do, ln in zip(batch.src.tolist(), batch.arena_off.tolist(),
                                       lens.tolist()):
@@ -300,22 +307,19 @@ class GpuBackend:
                                                      non_blocking=True)
                 ev = torch.cuda.Event()
                 ev.record(self.copy_stream)
-            self.lane_streams[lane].wait_event(ev)
-        self.hh.state_init(self.keys, n, d[24 * n:28 * n].view(torch.int32), self.states,
-                           d[28 * n:32 * n].view(torch.int32))
-
-    @staticmethod
-    def _put(h: np.ndarray, off: int, arr: np.ndarray, dt) -> Tuple[int, int]:
-        a = np.ascontiguousarray(arr, dtype=dt)
-        nb = a.nbytes
-        h[off:off + nb] = a.view(np.uint8)
-        return off, nb
+            self.compute_stream.wait_event(ev)
+        d = self.adm_dev[i]
+        self.hh.state_init_raw(self.keys, n, d + 24 * n, self.states, d + 28 * n,
+                               self.compute_stream.cuda_stream)
+        ev = self.adm_events[i]
+        ev.record(self.compute_stream)
+        return (ev, None)
 
     def launch(self, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens, fin_widths,
                lane: int = 0):
         """One iteration of a lane: fold whole-packet chunks into the states of
         upd_slots, finish fin_slots, all in one kernel launch on the lane's
-        stream (lane 0: the current stream).  Arrays of equal length per
+        stream (lane 0: the compute stream).  Arrays of equal length per
         group.  Returns a ticket for done()/wait()/results()."""
         if lane == 0:
             return self._launch(0, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens,
@@ -329,59 +333,34 @@ class GpuBackend:
 
     def _launch(self, lane, upd_slots, upd_offs, upd_lens, fin_slots, fin_offs, fin_lens,
                 fin_widths):
-        torch, hh = self.torch, self.hh
         i = self.k[lane] % self.RING
         self.k[lane] += 1
-        n_upd, n_fin = len(upd_slots), len(fin_slots)
-        n = n_upd + n_fin
+        nu, nf = len(upd_slots), len(fin_slots)
+        n = nu + nf
         res = None
         if n:
-            h = self.h_meta[lane][i].numpy()
-            # updates first, then finals; a final's words go to out[4 * j]
-            # for its rank j among the finals
-            out_offs = np.zeros(n, np.int64)
-            out_offs[n_upd:] = 4 * np.arange(n_fin, dtype=np.int64)
-            widths = np.zeros(n, np.uint8)
-            widths[n_upd:] = fin_widths
-            regs = {}
-            off = 0
-            for name, parts, dt in (("o", (upd_offs, fin_offs), np.int64),
-                                    ("l", (upd_lens, fin_lens), np.int64),
-                                    ("oo", (out_offs,), np.int64),
-                                    ("s", (upd_slots, fin_slots), np.int32),
-                                    ("w", (widths,), np.uint8)):
-                arr = np.concatenate([np.asarray(a, dt) for a in parts])
-                off = (off + 7) // 8 * 8
-                regs[name] = self._put(h, off, arr, dt)
-                off += regs[name][1]
-            if lane != 0:
-                # the long lane's kernel reads the item lists from the pinned
-                # staging set and writes the hashes into the pinned result
-                # set: its stream carries no copies (a copy queued behind a
-                # long iteration could hold up the host)
-                mb = self.meta_dev[lane][i]
-                hh.state_step_raw(self.states, self.data, mb + regs["o"][0], mb + regs["l"][0],
-                                  mb + regs["w"][0], self.res_dev[lane][i],
-                                  self.max_slots * 4, mb + regs["oo"][0], mb + regs["s"][0], n,
-                                  self.lane_streams[lane].cuda_stream)
-                if n_fin:
-                    res = self.h_res[lane][i][:n_fin]
-            else:
-                d = self.d_meta[lane][i]
-                d[:off].copy_(self.h_meta[lane][i][:off], non_blocking=True)
-
-                def view(name, dt):
-                    o, nb = regs[name]
-                    return d[o:o + nb].view(dt)
-
-                out = self.out[lane]
-                hh.state_step(self.states, self.data, view("o", torch.int64),
-                              view("l", torch.int64), view("w", torch.uint8), out.view(-1),
-                              view("oo", torch.int64), view("s", torch.int32))
-                if n_fin:
-                    # results land compacted in launch order: one contiguous copy out
-                    res = self.h_res[lane][i][:n_fin]
-                    res.copy_(out[:n_fin], non_blocking=True)
+            # item lists in the pinned staging set: offsets, lengths, output
+            # offsets (u64), state slots (u32), widths (u8); updates first,
+            # then finals, whose words go to the result set at 4 * rank
+            h = self.meta_np[lane][i]
+            w64 = h[:24 * n].view(np.int64)
+            w64[:nu] = upd_offs
+            w64[nu:n] = fin_offs
+            w64[n:n + nu] = upd_lens
+            w64[n + nu:2 * n] = fin_lens
+            w64[2 * n:2 * n + nu] = 0
+            w64[2 * n + nu:3 * n] = np.arange(0, 4 * nf, 4)
+            s32 = h[24 * n:28 * n].view(np.int32)
+            s32[:nu] = upd_slots
+            s32[nu:] = fin_slots
+            h[28 * n:28 * n + nu] = 0
+            h[28 * n + nu:29 * n] = fin_widths
+            mb = self.meta_dev[lane][i]
+            self.hh.state_step_raw(self.states, self.data, mb, mb + 8 * n, mb + 28 * n,
+                                   self.res_dev[lane][i], self.max_slots * 4, mb + 16 * n,
+                                   mb + 24 * n, n, self.lane_streams[lane].cuda_stream)
+            if nf:
+                res = self.res_np[lane][i][:nf]
         # events are reused round the staging ring (a set is re-recorded only
         # after the scheduler has harvested its previous launch)
         ev = self.events[lane][i]
@@ -403,8 +382,7 @@ class GpuBackend:
     def results(self, ticket) -> Optional[np.ndarray]:
         """(n_fin, 4) uint64 hash words of the ticket's finished items, in the
         order they were launched."""
-        ev, res = self._resolve(ticket)
-        return None if res is None else res.numpy().view(np.uint64)
+        return self._resolve(ticket)[1]
 
     def feed_submit(self, slots, offsets, lengths, widths, key_idx) -> int:
         """Hand admitted requests to the feed (taken in this order; offsets
@@ -501,12 +479,17 @@ class Server:
         back in its previous state after): a full pass over a process that
         holds a few hundred thousand objects stops the loop for about 40 ms,
         which held every request in flight that long in some runs.  The loop
-        makes no reference cycles of its own."""
+        makes no reference cycles of its own.  With real sleeps, the thread's
+        timer slack is 1 us while the loop runs (then restored)."""
         was_enabled = gc.isenabled()
         gc.disable()
+        # real sleeps: a fine timer slack while the loop runs
+        slack = _timer_slack(1000) if self.sleep is time.sleep else -1
         try:
             return self._run(requests)
         finally:
+            if slack >= 0:
+                _timer_slack(slack)
             if was_enabled:
                 gc.enable()
 
@@ -544,7 +527,8 @@ class Server:
         # per lane: (ticket, finishing slots) in launch order
         inflight = [collections.deque() for _ in range(self.lanes)]
         feed = self.long_mode == "feed"
-        fed = np.zeros(S, bool)             # handed to the feed, result not yet seen
+        feed_wait = []                      # slots ready for the feed, not yet submitted
+        fed_slots = np.zeros(0, np.int64)   # handed to the feed, result not yet seen
         key_of = np.zeros(S, np.int64)      # key index of the slot's request
         # with device ingress the kernels read a request where it arrived
         # (offsets into the ingress buffer), and a feed request needs no
@@ -644,6 +628,8 @@ class Server:
                 if direct:
                     # long requests skip admission: the feed reads their bytes
                     # where they arrived, so they are ready at once
+                    if is_long.any():
+                        feed_wait.append(r_slot[ridx[is_long]])
                     ridx = ridx[~is_long]
                     is_long = is_long[~is_long]
                 if ridx.size:
@@ -656,28 +642,34 @@ class Server:
                         gated.append((adm, longs))
             # long-lane requests whose admission has completed may advance
             while gated and self.backend.done(gated[0][0]):
-                ready[gated.popleft()[1]] = True
+                longs = gated.popleft()[1]
+                ready[longs] = True
+                if feed:
+                    feed_wait.append(longs)
             # feed mode: long requests whose admission is done go whole to the
             # feed, longest first
             if feed:
-                g = np.flatnonzero(busy & (lane == 1) & ready)
-                if g.size:
+                if feed_wait:
+                    g = feed_wait[0] if len(feed_wait) == 1 else np.concatenate(feed_wait)
                     g = g[np.argsort(-length[g], kind="stable")]
                     tk = self.backend.feed_submit(g, base[g],
                                                   length[g], width[g], key_of[g])
                     if tk:  # else the queue is full: they wait for the next pass
+                        feed_wait = []
                         fticket[g] = tk + np.arange(g.size, dtype=np.uint64)
-                        fed[g] = True
+                        fed_slots = np.concatenate([fed_slots, g])
                         busy[g] = False
                         n_busy -= g.size
                         n_fed += g.size
                         self.feed_submits += 1
+                    else:
+                        feed_wait = [g]
                 if n_fed:
-                    sub = np.flatnonzero(fed)
                     rows = self.backend.feed_rows()
-                    fin = sub[rows[sub, 4] == fticket[sub]]
-                    if fin.size:
-                        fed[fin] = False
+                    hit = rows[fed_slots, 4] == fticket[fed_slots]
+                    if hit.any():
+                        fin = fed_slots[hit]
+                        fed_slots = fed_slots[~hit]
                         n_fed -= fin.size
                         retire(fin, rows[fin, :4].copy())
                     self.backend.feed_poll()
