@@ -656,6 +656,25 @@ def state_step_raw(states: torch.Tensor, data: torch.Tensor, offsets: int, lengt
                                _vp(out), out_words, _vp(out_offsets), n, _vp(stream)))
 
 
+def hash_raw(keys: torch.Tensor, data: torch.Tensor, key_idx: int, offsets: int, lengths: int,
+             n: int, out: int, width: int = 4, path: str = "lane4", stream: int = 0) -> None:
+    """hash(...) with the message arrays and the output given as device
+    addresses (e.g. from pinned_device_pointer; key_idx 0: key 0 for every
+    message), n messages, out n * width words, and an explicit stream
+    handle; keys and data are device tensors as for hash."""
+    _dev(keys, "keys", _W64, 2)
+    _dev(data, "data", (torch.uint8,), 1)
+    if width not in (1, 2, 4):
+        raise ValueError("width must be 1, 2 or 4 words")
+    if path not in PATHS:
+        raise ValueError("path must be one of %s" % sorted(PATHS))
+    if not (offsets and lengths and out):
+        raise ValueError("offsets, lengths and out must be given")
+    _check(lib().hh_hash_path(PATHS[path], width, _ptr(keys), keys.shape[0], _vp(key_idx or None),
+                              _ptr(data), data.numel(), _vp(offsets), _vp(lengths), n, _vp(out),
+                              _vp(stream)))
+
+
 def state_init_raw(keys: torch.Tensor, n: int, key_idx: int, states: torch.Tensor,
                    state_idx: int, stream: int) -> None:
     """state_init with key_idx and state_idx given as device addresses (e.g.

@@ -211,9 +211,11 @@ class GpuBackend:
         # hardware queue with the compute stream, or the short requests'
         # iterations would wait behind a long iteration: pick streams that are
         # measured to run concurrently with it
-        extra = hh.independent_streams(2 if source == "host" else 1,
-                                       avoid=[self.compute_stream])
-        self.copy_stream = extra[1] if source == "host" else torch.cuda.Stream()
+        extra = hh.independent_streams(2, avoid=[self.compute_stream])
+        # the second extra stream carries the admission copies (host
+        # ingress) or the whole lane's launches (device ingress)
+        self.copy_stream = extra[1] if source == "host" else None
+        self.whole_stream = extra[1] if source == "device" else None
         self.lane_streams = [self.compute_stream, extra[0]]
         # item metadata per staging set: offs u64, lens u64, out offs u64,
         # slots u32, widths u8 for at most max_slots items, each array 8-aligned
@@ -236,11 +238,24 @@ class GpuBackend:
         self.meta_dev = [[hh.pinned_device_pointer(t) for t in ring] for ring in self.h_meta]
         self.res_dev = [[hh.pinned_device_pointer(t) for t in ring] for ring in self.h_res]
         self.adm_dev = [hh.pinned_device_pointer(t) for t in self.h_adm]
+        # the whole lane (device ingress): message lists (offsets u64,
+        # lengths u64, key index u32) and 4-word results per staging set
+        self.whole = source == "device"
+        self.kw = 0
+        self.h_whole = [torch.empty(max_slots * 20 + 64, dtype=torch.uint8, pin_memory=True)
+                        for _ in range(self.RING)] if self.whole else []
+        self.h_wres = [torch.empty((max_slots, 4), dtype=torch.int64, pin_memory=True)
+                       for _ in range(self.RING)] if self.whole else []
+        self.whole_dev = [hh.pinned_device_pointer(t) for t in self.h_whole]
+        self.wres_dev = [hh.pinned_device_pointer(t) for t in self.h_wres]
+        self.whole_np = [t.numpy() for t in self.h_whole]
+        self.wres_np = [t.numpy().view(np.uint64) for t in self.h_wres]
         self.meta_np = [[t.numpy() for t in ring] for ring in self.h_meta]
         self.res_np = [[t.numpy().view(np.uint64) for t in ring] for ring in self.h_res]
         self.adm_np = [t.numpy() for t in self.h_adm]
         self.launcher = concurrent.futures.ThreadPoolExecutor(max_workers=1)
         self.events = [[torch.cuda.Event() for _ in range(self.RING)] for _ in range(self.LANES)]
+        self.whole_events = [torch.cuda.Event() for _ in range(self.RING)]
         self.adm_events = [torch.cuda.Event() for _ in range(self.RING)]
         # The first launch on a stream sets the stream up inside the runtime:
         # it took about 5 ms and held up every other launch of the process
@@ -249,8 +264,7 @@ class GpuBackend:
         # request arrives.
         self._warm = torch.zeros(1, dtype=torch.int64, device="cuda")
         self._warm_stream(self.compute_stream)
-        if source == "host":
-            self._warm_stream(self.copy_stream)
+        self._warm_stream(extra[1])
         self.launcher.submit(self._warm_stream, self.lane_streams[1]).result()
         # With device ingress every kernel reads a request where it arrived
         # (reads_source: admission only resets states, there is no copy to
@@ -367,6 +381,26 @@ class GpuBackend:
         ev.record(self.lane_streams[lane])
         return (ev, res)
 
+    def launch_whole(self, offsets, lengths, key_idx):
+        """Hash requests whole in one launch on the whole lane's stream (device
+        ingress: offsets into the ingress buffer; no state, no admission).
+        Returns a ticket whose results() are the requests' 4-word hashes in
+        this order.  At most RING - 1 of these may be in flight."""
+        i = self.kw % self.RING
+        self.kw += 1
+        n = len(offsets)
+        h = self.whole_np[i]
+        w64 = h[:16 * n].view(np.int64)
+        w64[:n] = offsets
+        w64[n:] = lengths
+        h[16 * n:20 * n].view(np.int32)[:] = key_idx
+        d = self.whole_dev[i]
+        self.hh.hash_raw(self.keys, self.data, d + 16 * n, d, d + 8 * n, n, self.wres_dev[i], 4,
+                         "lane4", self.whole_stream.cuda_stream)
+        ev = self.whole_events[i]
+        ev.record(self.whole_stream)
+        return (ev, self.wres_np[i][:n])
+
     @staticmethod
     def _resolve(ticket):
         return ticket.result() if isinstance(ticket, concurrent.futures.Future) else ticket
@@ -426,7 +460,7 @@ class Server:
                  sleep=time.sleep, run_ahead: int = 2, long_chunk_bytes: int = 1 << 20,
                  long_min_bytes: Optional[int] = None, poll_s: float = 5e-4,
                  long_mode: Optional[str] = None, feed_poll_s: float = 5e-5,
-                 stall_s: float = 60.0):
+                 stall_s: float = 60.0, whole_max_bytes: Optional[int] = None):
         for c in (chunk_bytes, long_chunk_bytes):
             if c <= 0 or c % 32:
                 raise ValueError("chunk sizes must be positive multiples of 32")
@@ -450,6 +484,18 @@ class Server:
         if long_min_bytes is None:
             long_min_bytes = (4 if long_mode == "feed" else 16) * chunk_bytes
         self.long_min = long_min_bytes
+        # requests up to whole_max_bytes take the whole lane when the backend
+        # has one (it hashes them where they arrived, in one launch on a
+        # stream of their own, with no state and no admission)
+        has_whole = bool(getattr(backend, "whole", False))
+        if whole_max_bytes is None:
+            whole_max_bytes = 8192 if has_whole else 0
+        if whole_max_bytes and not has_whole:
+            raise ValueError("whole_max_bytes needs a backend with a whole lane")
+        if whole_max_bytes > long_min_bytes and self.lanes > 1:
+            raise ValueError("whole_max_bytes must not exceed long_min_bytes")
+        self.whole_max = whole_max_bytes
+        self.whole_run_ahead = getattr(backend, "RING", 1 << 30) - 1
         self.feed_poll_s = feed_poll_s
         # the loop raises when admitted work makes no progress for this long
         self.stall_s = stall_s
@@ -525,7 +571,11 @@ class Server:
         ready = np.ones(S, bool)          # admission done (long lane: seen complete)
         gated: collections.deque = collections.deque()  # (admission ticket, slots)
         # per lane: (ticket, finishing slots) in launch order
-        inflight = [collections.deque() for _ in range(self.lanes)]
+        # (lane W: the whole lane)
+        inflight = [collections.deque() for _ in range(self.lanes + 1)]
+        W = self.lanes
+        whole_wait = []                     # whole-lane slots not yet launched
+        self.whole_launches = 0
         feed = self.long_mode == "feed"
         feed_wait = []                      # slots ready for the feed, not yet submitted
         fed_slots = np.zeros(0, np.int64)   # handed to the feed, result not yet seen
@@ -615,6 +665,8 @@ class Server:
                 owner[slots] = ridx
                 key_of[slots] = r_key[ridx]
                 lane[slots] = (r_len[ridx] > self.long_min) if self.lanes > 1 else 0
+                if self.whole_max:
+                    lane[slots[r_len[ridx] <= self.whole_max]] = W
                 self.reserved_bytes += int(need[:k].sum())
                 n_busy += k
                 head += k
@@ -623,6 +675,12 @@ class Server:
             adm = None
             if runs:
                 ridx = np.concatenate(runs)
+                if self.whole_max:
+                    # whole-lane requests skip admission altogether
+                    is_whole = lane[r_slot[ridx]] == W
+                    if is_whole.any():
+                        whole_wait.append(r_slot[ridx[is_whole]])
+                        ridx = ridx[~is_whole]
                 is_long = ((lane[r_slot[ridx]] == 1) if self.lanes > 1
                            else np.zeros(ridx.size, bool))
                 if direct:
@@ -676,13 +734,22 @@ class Server:
             # per lane, one chunk for every busy request of the lane (whole
             # packets, or its final rest), unless the lane is far enough ahead
             launched = False
+            if whole_wait and len(inflight[W]) < self.whole_run_ahead:
+                g = whole_wait[0] if len(whole_wait) == 1 else np.concatenate(whole_wait)
+                whole_wait = []
+                ticket = self.backend.launch_whole(base[g], length[g], key_of[g])
+                busy[g] = False
+                n_busy -= g.size
+                inflight[W].append((ticket, g))
+                self.whole_launches += 1
+                launched = True
             for ln in range(self.lanes):
                 if feed and ln == 1:
                     continue
                 if len(inflight[ln]) > self.lane_run_ahead[ln]:
                     continue
                 idx = (np.flatnonzero(busy & (lane == ln) & ready) if self.lanes > 1
-                       else np.flatnonzero(busy))
+                       else np.flatnonzero(busy & (lane == 0)))
                 if not idx.size:
                     continue
                 chunk = self.chunks[ln]
@@ -701,21 +768,22 @@ class Server:
                 iterations += 1
                 launched = True
             # harvest what has finished; lane 0 blocks when too far ahead
-            for ln in range(self.lanes):
+            for ln in range(self.lanes + 1):
                 while inflight[ln] and self.backend.done(inflight[ln][0][0]):
                     harvest(ln, False)
             while len(inflight[0]) > self.lane_run_ahead[0]:
                 harvest(0, True)
             if not launched:
-                if inflight[0]:
+                if inflight[0] and not inflight[W]:
                     harvest(0, True)  # short iterations: wait for the oldest
                 elif (any(inflight) or gated or n_fed) and head == arrived:
-                    # only long work or admissions in flight: sleep until the
-                    # next arrival (at most poll_s, or feed_poll_s while the
-                    # feed holds requests)
+                    # only long work, whole-lane launches or admissions in
+                    # flight: sleep until the next arrival (at most poll_s, or
+                    # feed_poll_s while the feed or the whole lane holds
+                    # requests)
                     nxt = (arrival[arrived] - (self.clock() - t0) if arrived < n_total
                            else self.poll_s)
-                    cap = self.feed_poll_s if n_fed else self.poll_s
+                    cap = self.feed_poll_s if (n_fed or inflight[W]) else self.poll_s
                     self.sleep(max(0.0, min(cap, nxt)))
             if (not n_busy and not any(inflight) and not gated and not n_fed
                     and head == arrived and arrived < n_total):
@@ -757,6 +825,7 @@ class Server:
             "chunk_bytes": self.chunk, "budget_bytes": self.budget,
             "max_bytes_in_flight": self.max_bytes_in_flight,
             "long_mode": self.long_mode, "long_min_bytes": self.long_min,
+            "whole_max_bytes": self.whole_max, "whole_launches": self.whole_launches,
         }
 
 

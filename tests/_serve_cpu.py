@@ -25,7 +25,7 @@ class CpuBackend:
     LANES = 2
 
     def __init__(self, keys, payload, arena_bytes, max_slots, clock, ns_per_byte=0.05,
-                 launch_s=20e-6, reads_source=False):
+                 launch_s=20e-6, reads_source=False, whole=False):
         self.keys = np.asarray(keys, np.uint64).reshape(-1, 4)
         self.payload = payload
         self.arena = np.zeros(max(arena_bytes, 256), np.uint8)
@@ -42,6 +42,12 @@ class CpuBackend:
         # into the payload), admission copies nothing
         self.reads_source = reads_source
         self.data = payload if reads_source else self.arena
+        # whole: requests hashed whole from where they arrived, in one
+        # launch, with no state (needs reads_source, as on the device)
+        assert not whole or reads_source
+        self.whole = whole
+        self.whole_launched = []   # lengths per whole launch
+        self.admitted = 0          # requests admitted (states reset)
 
     def _check_no_overlap(self):
         spans = sorted((o, o + max(n, 1)) for o, n in self.live.values())
@@ -49,6 +55,7 @@ class CpuBackend:
             assert a1 <= b0, "arena regions overlap"
 
     def admit(self, batch):
+        self.admitted += len(batch.slot)
         for src, off, n, key, slot in zip(batch.src.tolist(), batch.arena_off.tolist(),
                                           batch.length.tolist(), batch.key_idx.tolist(),
                                           batch.slot.tolist()):
@@ -83,6 +90,18 @@ class CpuBackend:
             del self.live[slot]
             biggest = max(biggest, n)
         self.clock.t += self.launch_s + biggest * self.ns_per_byte * 1e-9
+        return res
+
+    def launch_whole(self, offsets, lengths, key_idx):
+        assert self.whole
+        res = np.zeros((len(offsets), 4), np.uint64)
+        for i, (off, n, k) in enumerate(zip(np.asarray(offsets).tolist(),
+                                            np.asarray(lengths).tolist(),
+                                            np.asarray(key_idx).tolist())):
+            res[i] = oracle.hash_words(self.keys[k], self.payload[off:off + n], 4)
+        self.whole_launched.append(np.asarray(lengths).copy())
+        self.clock.t += self.launch_s + max([0] + np.asarray(lengths).tolist()) * \
+            self.ns_per_byte * 1e-9
         return res
 
     def done(self, ticket):

@@ -194,6 +194,35 @@ def test_feed_mode_results_equal_one_shot(reads_source):
         assert r.result == tuple(oracle.hash_words(tr.keys[r.key_idx], msg, r.width)), r.rid
 
 
+@pytest.mark.parametrize("feed", [False, True])
+def test_whole_lane_results_equal_one_shot(feed):
+    # requests up to whole_max_bytes are hashed whole in one launch each pass,
+    # from where they arrived, with no admission and no state; the others
+    # take lane 0 (and the feed); every result is exact
+    from _serve_cpu import FeedCpuBackend
+    tr = _trace(300, 3000.0, hi=9000, seed=57)
+    clock = VirtualClock()
+    reqs = serve.requests_from_trace(tr)
+    cls = FeedCpuBackend if feed else CpuBackend
+    be = cls(tr.keys, tr.data, 1 << 18, 128, clock, reads_source=True, whole=True)
+    srv = serve.Server(be, budget_bytes=1 << 18, chunk_bytes=64, long_min_bytes=2048,
+                       whole_max_bytes=256, clock=clock, sleep=clock.sleep)
+    m = srv.run(reqs)
+    assert m["completed"] == len(reqs) and m["whole_launches"] == len(be.whole_launched)
+    lens = np.concatenate(be.whole_launched)
+    assert lens.size == sum(r.length <= 256 for r in reqs) and lens.max() <= 256
+    # whole-lane requests were never admitted (no state was reset for
+    # them), nor were the feed's, which it also reads where they arrived
+    admitted = sum(256 < r.length and (r.length <= 2048 or not feed) for r in reqs)
+    assert be.admitted == admitted
+    for r in reqs:
+        msg = tr.data[r.src:r.src + r.length]
+        assert r.result == tuple(oracle.hash_words(tr.keys[r.key_idx], msg, r.width)), r.rid
+    with pytest.raises(ValueError):   # the whole lane needs a backend that has one
+        serve.Server(CpuBackend(tr.keys, tr.data, 1 << 17, 64, clock), budget_bytes=1 << 17,
+                     whole_max_bytes=256)
+
+
 def test_chunked_long_lane_still_selectable():
     from _serve_cpu import FeedCpuBackend
     tr = _trace(80, 3000.0, hi=9000, seed=53)
