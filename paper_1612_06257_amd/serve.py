@@ -181,7 +181,12 @@ class GpuBackend:
     iterations.  Admission runs on the compute stream; the lane 1
     stream only ever receives that lane's iterations, or the feed's
     persistent kernel (feed_submit), which hashes a long request whole and
-    writes its result into host memory."""
+    writes its result into host memory.
+
+    With device ingress the backend also has a whole lane (launch_whole): a
+    stream of its own on which one launch hashes a batch of short requests
+    whole, where they arrived, with no state and no admission, writing
+    their 4-word hashes into a pinned result set."""
 
     RING = 6   # staging sets per lane; more than the scheduler's run-ahead + 1
     LANES = 2
@@ -453,7 +458,13 @@ class Server:
     longest chunk of one.  long_mode="chunks": long requests advance
     long_chunk_bytes per iteration on their own stream.  Every lane keeps its
     own work in flight, so long requests never stretch the short requests'
-    iterations."""
+    iterations.
+
+    With a backend that has a whole lane, requests up to whole_max_bytes
+    (8 KiB by default) skip admission and lane 0: each pass hashes the ones
+    admitted since the last in one launch on that lane's stream, so they
+    wait neither for lane 0's queued iterations nor for the 64 KiB chunks in
+    them."""
 
     def __init__(self, backend, budget_bytes: int, chunk_bytes: int = 1 << 16,
                  max_active: Optional[int] = None, clock=time.perf_counter,
@@ -839,7 +850,8 @@ def serve_trace(trace, budget_bytes: int = 32 << 30, chunk_bytes: int = 1 << 16,
                 max_slots: int = 16384, source: str = "device", time_scale: float = 1.0,
                 feed_waves: int = 64, **server_kw):
     """Run one trace on the GPU; returns (metrics, requests).  server_kw go to
-    Server (long_mode, long_chunk_bytes, long_min_bytes, poll_s, run_ahead);
+    Server (long_mode, long_chunk_bytes, long_min_bytes, whole_max_bytes, poll_s,
+    run_ahead);
     feed_waves sizes the backend's feed (one dispatcher wave, the others
     hashing up to 16 requests each)."""
     reqs = requests_from_trace(trace)
@@ -934,6 +946,9 @@ def main(argv=None):
                          "with the feed, 16 chunked)")
     ap.add_argument("--feed-waves", type=int, default=64,
                     help="feed workgroups: one dispatcher, the others 16 requests each")
+    ap.add_argument("--whole-max", type=int, default=None,
+                    help="requests up to this many bytes take the whole lane (device "
+                         "ingress; default 8192, 0 turns it off)")
     ap.add_argument("--poll-us", type=float, default=500.0)
     ap.add_argument("--max-slots", type=int, default=16384,
                     help="request states held on the device (128 B each)")
@@ -943,7 +958,7 @@ def main(argv=None):
     loads = tuple(float(x) for x in args.loads.split(",") if x)
     kw = dict(long_chunk_bytes=args.long_chunk, long_min_bytes=args.long_min,
               poll_s=args.poll_us * 1e-6, max_slots=args.max_slots, long_mode=args.long_mode,
-              feed_waves=args.feed_waves)
+              feed_waves=args.feed_waves, whole_max_bytes=args.whole_max)
     rates = [float(x) for x in args.rates.split(",") if x] if args.rates else None
     for p in load_sweep(args.requests, loads, args.chunk, int(args.budget_gib * 2**30), args.source,
                         rates=rates, **kw):
