@@ -17,20 +17,25 @@ def hh():
     return require_gpu()
 
 
-@pytest.mark.parametrize("source,long_chunk,long_mode", [
-    ("device", 1 << 20, "feed"), ("host", 1 << 20, "feed"), ("device", 1 << 20, "chunks"),
-    ("host", 1 << 20, "chunks"), ("device", 8192, "chunks")])
-def test_serving_results_match_alone_and_oracle(hh, source, long_chunk, long_mode):
-    # requests over 64 KiB take the long lane (its own stream): whole, in the
-    # feed's persistent kernel, or in chunked iterations (with 8 KiB chunks,
-    # several long-lane iterations beside the short ones)
-    announce("serving", source, long_chunk, long_mode)
+@pytest.mark.parametrize("source,long_chunk,long_mode,whole_max", [
+    ("device", 1 << 20, "feed", None), ("host", 1 << 20, "feed", None),
+    ("device", 1 << 20, "chunks", None), ("host", 1 << 20, "chunks", None),
+    ("device", 8192, "chunks", None), ("device", 1 << 20, "feed", 0),
+    ("device", 1 << 20, "feed", 16384)])
+def test_serving_results_match_alone_and_oracle(hh, source, long_chunk, long_mode, whole_max):
+    # requests over four chunks (16 KiB; chunked: sixteen, 64 KiB) take the
+    # long lane (its own stream): whole, in the feed's persistent kernel, or
+    # in chunked iterations (with 8 KiB chunks, several long-lane iterations
+    # beside the short ones); with device ingress, requests up to 8 KiB (or
+    # whole_max; 0: none) take the whole lane
+    announce("serving", source, long_chunk, long_mode, whole_max)
     tr = workloads.serving_trace(400, 20000.0, lo=1, hi=200000, n_keys=16, seed=99)
     tr.lengths[::23] = 0
     budget = 8 << 20
     backend = serve.GpuBackend(tr.keys, tr.data, budget, 256, source)
     srv = serve.Server(backend, budget_bytes=budget, chunk_bytes=4096,
-                       long_chunk_bytes=long_chunk, long_mode=long_mode)
+                       long_chunk_bytes=long_chunk, long_mode=long_mode,
+                       whole_max_bytes=whole_max)
     reqs = serve.requests_from_trace(tr)
     try:
         m = srv.run(reqs)
@@ -38,6 +43,7 @@ def test_serving_results_match_alone_and_oracle(hh, source, long_chunk, long_mod
         backend.close()
     assert m["completed"] == len(reqs)
     assert m["max_bytes_in_flight"] <= budget
+    assert (m["whole_launches"] > 0) == (source == "device" and whole_max != 0)
     # alone: each request through the one-shot batched kernel, one message per call
     keys = torch.from_numpy(tr.keys).view(torch.int64).cuda()
     data = torch.from_numpy(tr.data).cuda()
@@ -210,8 +216,9 @@ def test_widths_other_than_1_2_4_write_nothing(hh):
 def test_serving_at_benchmark_settings(hh, arrivals, long_mode):
     # the settings the benchmark's serving runs use: 64 KiB chunks, 1 MiB
     # long-lane chunks, power-law lengths on [8 B, 16 MiB], 64 keys, widths
-    # 1/2/4, device ingress; a few requests of 4-16 MiB span many long-lane
-    # iterations beside the short ones.  Every result equals the oracle and
+    # 1/2/4, device ingress (requests up to 8 KiB in the whole lane); a few
+    # requests of 4-16 MiB span many long-lane iterations beside the short
+    # ones.  Every result equals the oracle and
     # the request hashed on its own by the one-shot batched path.
     from paper_1612_06257_amd import workloads as W
     announce("serving at bench settings", arrivals, long_mode)
