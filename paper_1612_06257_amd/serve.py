@@ -622,8 +622,9 @@ class Server:
             t_done[ridx] = t
             status[ridx] = 2
             owner[fin] = -1
-            self.arena.release_many(list(zip(held[fin].tolist(),
-                                             np.maximum(length[fin], 1).tolist())))
+            if not in_place:
+                self.arena.release_many(list(zip(held[fin].tolist(),
+                                                 np.maximum(length[fin], 1).tolist())))
             self.reserved_bytes -= int(resv[fin].sum())
             self.free_slots.extend(fin.tolist())
             self.n_finished += len(fin)
@@ -657,14 +658,19 @@ class Server:
                 if k == 0:
                     break  # back-pressure: wait for completions
                 gran = r_gran[head:head + k]
-                off = self.arena.alloc(int(gran.sum()))
-                if off is None:
-                    # no contiguous range for the run: the head request alone
-                    k, gran = 1, gran[:1]
-                    off = self.arena.alloc(int(gran[0]))
+                if in_place:
+                    # the kernels read the payloads where they arrived: the
+                    # budget alone binds, no arena range is needed
+                    offs = np.full(k, -1, np.int64)
+                else:
+                    off = self.arena.alloc(int(gran.sum()))
                     if off is None:
-                        break  # fragmented: wait for completions
-                offs = off + np.cumsum(gran) - gran
+                        # no contiguous range for the run: the head request alone
+                        k, gran = 1, gran[:1]
+                        off = self.arena.alloc(int(gran[0]))
+                        if off is None:
+                            break  # fragmented: wait for completions
+                    offs = off + np.cumsum(gran) - gran
                 slots = np.array(self.free_slots[-k:][::-1], np.int64)
                 del self.free_slots[-k:]
                 ridx = np.arange(head, head + k)

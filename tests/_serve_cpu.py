@@ -63,7 +63,10 @@ class CpuBackend:
             if not self.reads_source:
                 self.arena[off:off + n] = self.payload[src:src + n]
             self.cats[slot] = oracle.Cat(self.keys[key])
-            self.live[slot] = (off, n)
+            if self.reads_source:
+                assert off == -1   # no arena range: the budget alone binds
+            else:
+                self.live[slot] = (off, n)
         self._check_no_overlap()
         return ("admission",)
 
@@ -87,7 +90,7 @@ class CpuBackend:
             c = self.cats.pop(slot)
             c.append(self.data[off:off + n])
             res[i] = c.finish(4)
-            del self.live[slot]
+            self.live.pop(slot, None)
             biggest = max(biggest, n)
         self.clock.t += self.launch_s + biggest * self.ns_per_byte * 1e-9
         return res
@@ -142,7 +145,7 @@ class FeedCpuBackend(CpuBackend):
                 c = oracle.Cat(self.keys[k])
             else:
                 c = self.cats.pop(slot)
-                del self.live[slot]
+                self.live.pop(slot, None)
             c.append(self.data[off:off + n])
             self.rows[slot, :4] = c.finish(4)
             self.rows[slot, 4] = t + i
