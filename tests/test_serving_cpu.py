@@ -91,11 +91,15 @@ def test_results_equal_one_shot_hashes(chunk, reads_source):
     assert be.launches == m["iterations"]
 
 
-def test_admission_respects_budget_and_back_pressure():
+@pytest.mark.parametrize("reads_source", [False, True])
+def test_admission_respects_budget_and_back_pressure(reads_source):
+    # with payloads copied into the arena, or read where they arrived (then
+    # the budget's sum alone binds, with no arena range)
     tr = _trace(200, 1e6, hi=20000, seed=3)   # everything arrives at once
     budget = 40000
-    m, reqs, be = _run(tr, budget=budget, chunk=512)
+    m, reqs, be = _run(tr, budget=budget, chunk=512, reads_source=reads_source)
     assert m["max_bytes_in_flight"] <= budget
+    assert m["max_bytes_in_flight"] > budget // 2   # the budget did bind
     big = [r for r in reqs if serve.Server.reservation(r.length) > budget]
     assert all(r.status == "rejected" for r in big)
     assert all(r.status == "done" for r in reqs if r not in big)
