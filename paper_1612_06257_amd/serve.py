@@ -512,7 +512,9 @@ class Server:
         self.stall_s = stall_s
         self.arena = Arena(budget_bytes)
         self.max_active = max_active or backend.max_slots
-        self.free_slots = list(range(backend.max_slots))[::-1]
+        # free state slots: a stack, slots[:n_free] (the top at the end)
+        self.free_slots = np.arange(backend.max_slots, dtype=np.int64)[::-1].copy()
+        self.n_free = backend.max_slots
         self.clock = clock
         self.sleep = sleep
         self.run_ahead = run_ahead
@@ -626,7 +628,8 @@ class Server:
                 self.arena.release_many(list(zip(held[fin].tolist(),
                                                  np.maximum(length[fin], 1).tolist())))
             self.reserved_bytes -= int(resv[fin].sum())
-            self.free_slots.extend(fin.tolist())
+            self.free_slots[self.n_free:self.n_free + fin.size] = fin
+            self.n_free += fin.size
             self.n_finished += len(fin)
 
         last_progress, seen_finished = 0.0, 0
@@ -641,8 +644,8 @@ class Server:
             arrived = int(np.searchsorted(arrival, now, side="right"))
             # admission, in arrival order, while a slot and budget are free
             runs = []
-            while head < arrived and self.free_slots and n_busy < self.max_active:
-                m = min(arrived - head, len(self.free_slots), self.max_active - n_busy)
+            while head < arrived and self.n_free and n_busy < self.max_active:
+                m = min(arrived - head, self.n_free, self.max_active - n_busy)
                 need = r_need[head:head + m]
                 over = np.flatnonzero(need > self.budget)
                 if over.size and over[0] == 0:
@@ -671,19 +674,24 @@ class Server:
                         if off is None:
                             break  # fragmented: wait for completions
                     offs = off + np.cumsum(gran) - gran
-                slots = np.array(self.free_slots[-k:][::-1], np.int64)
-                del self.free_slots[-k:]
+                slots = self.free_slots[self.n_free - k:self.n_free][::-1].copy()
+                self.n_free -= k
+                # the run is requests head .. head+k-1 (slices of the
+                # arrival-order arrays), in the slots just taken
+                sl = slice(head, head + k)
                 ridx = np.arange(head, head + k)
-                status[ridx], r_slot[ridx], r_off[ridx] = 1, slots, offs
-                r_resv[ridx], t_admit[ridx] = need[:k], now
-                busy[slots], length[slots], pos[slots] = True, r_len[ridx], 0
-                base[slots] = r_src[ridx] if in_place else offs
-                held[slots], resv[slots], width[slots] = offs, need[:k], r_width[ridx]
+                rl = r_len[sl]
+                status[sl], r_slot[sl], r_off[sl] = 1, slots, offs
+                r_resv[sl], t_admit[sl] = need[:k], now
+                busy[slots], length[slots], pos[slots] = True, rl, 0
+                base[slots] = r_src[sl] if in_place else offs
+                held[slots], resv[slots], width[slots] = offs, need[:k], r_width[sl]
                 owner[slots] = ridx
-                key_of[slots] = r_key[ridx]
-                lane[slots] = (r_len[ridx] > self.long_min) if self.lanes > 1 else 0
+                key_of[slots] = r_key[sl]
+                ln = (rl > self.long_min).astype(np.int8) if self.lanes > 1 else np.zeros(k, np.int8)
                 if self.whole_max:
-                    lane[slots[r_len[ridx] <= self.whole_max]] = W
+                    ln[rl <= self.whole_max] = W
+                lane[slots] = ln
                 self.reserved_bytes += int(need[:k].sum())
                 n_busy += k
                 head += k
