@@ -39,7 +39,7 @@ import gc
 import json
 import sys
 import time
-from typing import Dict, List, NamedTuple, Optional, Tuple
+from typing import List, NamedTuple, Optional, Tuple
 
 import numpy as np
 
