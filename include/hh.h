@@ -13,8 +13,10 @@
  * 256-bit hash lanes 0..3.
  *
  * Conventions for every entry point:
- *   - Pointers named in the argument list are DEVICE pointers unless noted.
- *     The caller owns every buffer and keeps it alive until the work enqueued
+ *   - Pointers named in the argument list are DEVICE pointers unless noted:
+ *     addresses the GPU can access, which includes the device address of
+ *     pinned host memory (hh_pinned_device_pointer) for the small index,
+ *     length and output arrays.  The caller owns every buffer and keeps it alive until the work enqueued
  *     on `stream` has finished; the library keeps no reference after return.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls only enqueue work; results are visible after stream or event
@@ -320,7 +322,9 @@ hh_status hh_release(void);
 
 /* Device address of pinned host memory (hipHostMalloc'd, e.g. a pinned
  * torch tensor), for kernels that read item lists from or write results to
- * host memory directly (the serving loop's long lane).  Returns
+ * host memory directly (the serving loop passes such addresses to
+ * hh_state_init, hh_state_step and hh_hash_path, so that no copy runs for
+ * them).  Returns
  * HH_ERR_INVALID_ARG for a null pointer and for memory the runtime does not
  * know as pinned. */
 hh_status hh_pinned_device_pointer(const void* host, void** device);
