@@ -107,6 +107,45 @@ def test_state_init_into_slots(hh):
     assert bool((states[untouched] == 7).all())
 
 
+def test_raw_calls_on_pinned_item_lists_match_tensor_calls(hh):
+    # the serving loop passes the device addresses of pinned host arrays
+    # (item lists in, hashes out) to hh_hash_path and hh_state_init: same
+    # results as the tensor calls on device arrays
+    announce("raw calls on pinned memory")
+    rng = np.random.default_rng(13)
+    n = 300
+    keys_np = rng.integers(0, 2**64, (7, 4), dtype=np.uint64)
+    keys = torch.from_numpy(keys_np).view(torch.int64).cuda()
+    lens = rng.integers(0, 9000, n)
+    lens[::31] = 0
+    offs = np.concatenate([[0], np.cumsum(lens[:-1] + 5)])
+    data_np = rng.integers(0, 256, int(offs[-1] + lens[-1] + 5), dtype=np.uint8)
+    data = torch.from_numpy(data_np).cuda()
+    kidx = rng.integers(0, 7, n).astype(np.int32)
+    pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+    p_offs, p_lens, p_kidx = pin(offs.astype(np.int64)), pin(lens.astype(np.int64)), pin(kidx)
+    p_out = torch.zeros((n, 4), dtype=torch.int64).pin_memory()
+    dev = hh.pinned_device_pointer
+    stream = torch.cuda.current_stream().cuda_stream
+    hh.hash_raw(keys, data, dev(p_kidx), dev(p_offs), dev(p_lens), n, dev(p_out), 4, "lane4",
+                stream)
+    want = hh.hash(keys, data, p_offs.cuda(), p_lens.cuda(), p_kidx.cuda(), 4)
+    torch.cuda.synchronize()
+    assert torch.equal(p_out, want.cpu())
+    for j in range(0, n, 37):
+        msg = data_np[offs[j]:offs[j] + lens[j]]
+        assert [int(x) for x in p_out[j].numpy().view(np.uint64)] == \
+            oracle.hash_words(keys_np[kidx[j]], msg, 4)
+    slots = pin(rng.permutation(500)[:n].astype(np.int32))
+    states = torch.full((500, hh.STATE_WORDS), 3, dtype=torch.int64, device="cuda")
+    hh.state_init_raw(keys, n, dev(p_kidx), states, dev(slots), stream)
+    dense = hh.state_init(keys, n, p_kidx.cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(states[slots.cuda().long()], dense)
+    with pytest.raises(ValueError):
+        hh.hash_raw(keys, data, 0, 0, dev(p_lens), n, dev(p_out), 4, "lane4", stream)
+
+
 def test_state_indices_past_the_array_are_skipped(hh):
     announce("state bounds")
     rng = np.random.default_rng(12)
