@@ -1,8 +1,11 @@
 """Serving loop: continuous batching of hash requests on one GPU.
 
 A request is (key index, payload bytes, output width 1/2/4 words).  The loop
-keeps every admitted request's payload on the device.  Requests up to four
-chunks (256 KiB) advance together in lane 0: each scheduler iteration gives
+keeps every admitted request's payload on the device.  With device ingress,
+requests up to 8 KiB take the whole lane: each pass hashes the ones that
+arrived since the last in one launch on a stream of their own, with no state
+and no admission kernel.  Other requests up to four chunks (256 KiB) advance
+together in lane 0: each scheduler iteration gives
 every active request one 64 KiB chunk (a multiple of 32 bytes, or its whole
 remainder), launched as one kernel that mixes the updates and the
 finalizations, with each request's 1024-bit state kept on the device between
@@ -22,7 +25,8 @@ launches overlap the device work; the scheduler keeps its request state in
 arrays and admits and retires requests in bulk.
 
     python -m paper_1612_06257_amd.serve [--requests N] [--loads 0.25,0.5,0.8]
-        [--rates R1,R2,...] [--long-mode feed|chunks]
+        [--rates R1,R2,...] [--long-mode feed|chunks] [--whole-max BYTES]
+        [--budget-gib G] [--source device|host]
 
 prints one JSON line per load point: offered rate, GB/s, requests/s,
 p50/p90/p99 latency.
