@@ -263,3 +263,15 @@ def test_stalled_loop_raises():
                        clock=clock, sleep=clock.sleep, stall_s=0.5)
     with pytest.raises(RuntimeError, match="no request finished"):
         srv.run(serve.requests_from_trace(tr))
+
+
+def test_timer_slack_set_and_restored():
+    # the loop sets a fine timer slack for real sleeps and puts the previous
+    # one back (where prctl is available; else the call reports -1)
+    prev = serve._timer_slack(1000)
+    if prev < 0:
+        pytest.skip("timer slack cannot be read here")
+    try:
+        assert serve._timer_slack(prev) == 1000
+    finally:
+        serve._timer_slack(prev)
